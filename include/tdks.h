@@ -1,0 +1,223 @@
+/*
+ * tdks.h -- C ABI of the MI355X (gfx950) real-time TDKS propagator with
+ * two-step Brillouin-zone sampling.
+ *
+ * Method: Sato, "Two-step Brillouin zone sampling for efficient computation
+ * of electron dynamics in solids", arXiv:2112.00920.
+ *   - TDKS equation for the periodic parts u_bk of the Bloch orbitals,
+ *     i d/dt u_bk = h_k(t) u_bk                                  (Sec. II.A, Eq. 1)
+ *   - h_k(t) = [p + k + A(t)]^2/2 + v_ion + v_Hxc[rho]          (Eq. 2)
+ *   - rho = sum_b BZ-average |u_bk|^2                            (Eq. 3)
+ *   - J = -(1/Omega) sum_b BZ-average <u_bk| pi_k |u_bk>,
+ *     pi_k = (1/i)[r, h_k]                                       (Eqs. 5-6)
+ *   - BZ average on a (shifted) Monkhorst-Pack grid             (Eqs. 7-8, 10)
+ *   - two-step scheme: N_H independent sub-simulations on shifted coarse
+ *     grids, observables averaged over them                      (Sec. II.B, Eq. 9)
+ *
+ * Numerics (the paper defers them to its production code; fixed here):
+ *   - real-space grid N1 x N2 x N3 along the lattice rows a_1, a_2, a_3;
+ *     4th-order finite differences (+-2 neighbours, periodic) for the kinetic
+ *     operator in the periodic-part gauge:
+ *       T_kappa = -1/2 L - i kappa . grad_FD + |kappa|^2 / 2, kappa = k + A(t);
+ *   - v_ion = Gaussian local potential + s and p Kleinman-Bylander projectors
+ *     per atom (Gaussian radial shape rc, shifted cut at Rc);
+ *   - v_Hxc = Hartree (Poisson by discrete Fourier transform, G = 0 and Nyquist
+ *     planes zeroed) + Slater exchange + Perdew-Zunger 81 correlation;
+ *   - propagator: explicit Taylor expansion of exp(-i h dt) to 4th order with
+ *     h evaluated at A(t_n + dt/2) and v_Hxc[rho(t_n)];
+ *   - the current after step n uses A(t_{n+1}).
+ *
+ * Conventions
+ *   - Atomic units throughout (bohr, hartree, a.u. of time).
+ *   - Orbital arrays passed across this ABI are complex128 (interleaved
+ *     re, im doubles) laid out [k][band][i3][i2][i1] (i1 fastest), normalised
+ *     to sum_r |u|^2 dV = 1 with dV = Omega / (N1 N2 N3).
+ *   - Fractional k are in units of the reciprocal vectors b_d
+ *     (a_d . b_e = 2 pi delta_de) and must already be wrapped the way the
+ *     caller wants them (the FD Hamiltonian is not periodic in k).
+ *   - Every function returns TDKS_OK (0) or a negative error code; the
+ *     message of the last error on the calling thread is tdks_last_error().
+ *   - A context is not thread-safe.  All device work of a context is ordered
+ *     on one internal HIP stream, which waits for the caller's stream at entry
+ *     and which the caller's stream waits for at exit of every call.
+ *   - Pointers marked HOST are host memory; pointers marked "where" are host
+ *     (TDKS_HOST) or device (TDKS_DEVICE) memory of the context's GPU.  Input
+ *     arrays are borrowed for the duration of the call only (copied).
+ */
+#ifndef TDKS_H
+#define TDKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define TDKS_OK 0
+#define TDKS_E_ARG (-1)         /* invalid argument or descriptor            */
+#define TDKS_E_OOM (-2)         /* device allocation failed                   */
+#define TDKS_E_HIP (-3)         /* HIP runtime error                          */
+#define TDKS_E_STATE (-4)       /* call not valid in the context's state      */
+#define TDKS_E_NUMERIC (-5)     /* non-finite current detected                */
+#define TDKS_E_UNSUPPORTED (-6) /* size or option outside the built kernels   */
+
+/* precision of the propagation arithmetic */
+#define TDKS_FP64 0       /* complex128 orbitals and arithmetic                   */
+#define TDKS_FP32_MIXED 1 /* complex64 orbitals, FP32 stencil/potential/projector
+                             arithmetic; FP64 density, current, Hxc and norms   */
+
+/* Hartree-exchange-correlation coupling */
+#define TDKS_HXC_SCF 0    /* v_Hxc recomputed from rho after every step          */
+#define TDKS_HXC_FROZEN 1 /* v_Hxc fixed to the array given in the descriptor    */
+#define TDKS_HXC_NONE 2   /* v_Hxc = 0                                           */
+
+/* memory location flags */
+#define TDKS_HOST 0
+#define TDKS_DEVICE 1
+
+/* current read-out modes */
+#define TDKS_PER_INSTANCE 0
+#define TDKS_PER_GROUP 1
+
+/* One pseudopotential species (Sec. II.A: local part + non-local projectors). */
+typedef struct tdks_species {
+    double D;  /* depth of the local Gaussian D exp(-r^2 / (2 w^2)) (Ha)        */
+    double w;  /* width of the local Gaussian (bohr); images within 15 w count  */
+    double rc; /* Gaussian radius of the KB projectors (bohr)                   */
+    double Rc; /* shifted-cut radius of the KB projectors (bohr); must be below
+                  half of the shortest lattice translation                      */
+    double Es; /* KB energy of the s channel (Ha)                               */
+    double Ep; /* KB energy of the three p channels (Ha)                        */
+} tdks_species;
+
+/* One independent TDDFT simulation (one sub-simulation of the two-step scheme,
+ * Sec. II.B procedure step 3, or one plain-method run). */
+typedef struct tdks_instance_desc {
+    double lattice[3][3];        /* rows a_1, a_2, a_3 (bohr)                      */
+    int grid[3];                 /* N1, N2, N3                                     */
+    int n_atoms;
+    const double *atom_frac;     /* HOST [n_atoms][3] fractional positions         */
+    const int *atom_species;     /* HOST [n_atoms] index into species               */
+    int n_species;
+    const tdks_species *species; /* HOST [n_species]                                */
+    int n_k;
+    const double *k_frac;        /* HOST [n_k][3] fractional k (units of b_d)       */
+    const double *k_weight;      /* HOST [n_k] BZ weights, or NULL for 1/n_k (Eq. 7) */
+    int n_bands;
+    const double *occ;           /* HOST [n_bands] occupations, or NULL for 2.0     */
+    int group;                   /* two-step group id (averaged in PER_GROUP mode)  */
+    const double *v_hxc_frozen;  /* HOST [N3][N2][N1], required iff TDKS_HXC_FROZEN */
+} tdks_instance_desc;
+
+typedef void *(*tdks_alloc_fn)(size_t bytes, void *user);
+typedef void (*tdks_free_fn)(void *ptr, void *user);
+
+typedef struct tdks_options {
+    int precision;        /* TDKS_FP64 or TDKS_FP32_MIXED                         */
+    double dt;            /* time step (a.u.)                                      */
+    int taylor_order;     /* must be 4                                             */
+    int hxc_mode;         /* TDKS_HXC_SCF / _FROZEN / _NONE                        */
+    void *stream;         /* caller's hipStream_t, or NULL for the null stream     */
+    tdks_alloc_fn alloc;  /* device allocator, or NULL for hipMalloc               */
+    tdks_free_fn free;    /* matching free, or NULL for hipFree                    */
+    void *alloc_user;     /* passed to alloc/free                                  */
+    int bands_per_group;  /* bands propagated by one workgroup (0 = all)           */
+    int k_per_group;      /* k-points handled by one workgroup (0 = 1)             */
+    int block_size;       /* threads per workgroup (0 = automatic)                 */
+    int graph_steps;      /* steps captured per HIP graph (0 = 16; <0 disables)    */
+} tdks_options;
+
+typedef struct tdks_ctx tdks_ctx;
+
+/* Fills *opt with defaults (FP64, dt = 0.02, order 4, SCF, automatic tiling). */
+void tdks_default_options(tdks_options *opt);
+
+/* Creates a context holding n_inst independent instances (Sec. II.B step 3:
+ * one TDDFT simulation per shift; instances may differ in cell, grid, k-count
+ * and band count).  Builds the grid, the local potential, the projector
+ * support tables and the k tables on the host, allocates the device memory
+ * through opt->alloc, and returns the context in *out.
+ * Errors: E_ARG (bad descriptor, e.g. Rc too large for the cell), E_OOM,
+ * E_HIP, E_UNSUPPORTED (grid larger than 8192 points, N_d > 64, more than
+ * 64 atoms, taylor_order != 4). */
+int tdks_create(const tdks_instance_desc *inst, int n_inst, const tdks_options *opt,
+                tdks_ctx **out);
+
+/* Releases all device memory and the internal stream.  NULL is allowed. */
+void tdks_destroy(tdks_ctx *ctx);
+
+/* Thread-local message of the last error ("" if none). */
+const char *tdks_last_error(void);
+
+/* Loads the orbitals of instance `inst` (complex128, [k][band][i3][i2][i1],
+ * `where` = TDKS_HOST or TDKS_DEVICE), rounding to complex64 for
+ * TDKS_FP32_MIXED.  Then computes rho (Eq. 3), v_Hxc (SCF mode), and the
+ * current before the field, J_pre = J(A = 0) (Sec. III.A: delta J is measured
+ * against J(t < 0)).  Resets the step counter of the context.
+ * Errors: E_ARG, E_HIP. */
+int tdks_load_orbitals(tdks_ctx *ctx, int inst, const void *u, int where);
+
+/* Advances every instance by n_steps Taylor-4 steps (Eq. 1) under the uniform
+ * vector potential table A_tab (HOST, [n_steps][2][3]: A(t_n + dt/2) used in
+ * h for step n, and A(t_{n+1}) used for the current recorded after it).  The
+ * current J^{n+1} (Eq. 5) of every instance is recorded after every step.
+ * Enqueued asynchronously (HIP graphs of opt->graph_steps steps); the host
+ * does no per-step work.  Errors: E_STATE (an instance not loaded), E_ARG,
+ * E_OOM (trace growth), E_HIP. */
+int tdks_step(tdks_ctx *ctx, int n_steps, const double *A_tab);
+
+/* Number of steps recorded since the last load (a load resets the record). */
+int tdks_steps_done(tdks_ctx *ctx);
+
+/* Copies the induced current delta J^n = J^n - J_pre for n = 1..steps_done
+ * into out (HOST).  mode TDKS_PER_INSTANCE: [n_inst][steps][3];
+ * TDKS_PER_GROUP: [n_groups][steps][3], the plain mean over the instances of
+ * each group in ascending group id (Eq. 9 / procedure step 4).  cap is the
+ * capacity of out in doubles; *n_written receives the number written.
+ * Synchronises.  Errors: E_ARG (cap too small), E_NUMERIC (a non-finite value;
+ * the message names the instance), E_HIP. */
+int tdks_current(tdks_ctx *ctx, int mode, double *out, size_t cap, size_t *n_written);
+
+/* J_pre of every instance, HOST out[n_inst][3].  Synchronises. */
+int tdks_current_pre(tdks_ctx *ctx, double *out);
+
+/* Current of the present orbitals of every instance at kappa = k + A
+ * (A HOST [3]), without propagating: out HOST [n_inst][3].  Synchronises. */
+int tdks_current_at(tdks_ctx *ctx, const double *A, double *out);
+
+/* Density rho (FP64, HOST out [N3][N2][N1]) of instance inst after the last
+ * step (or load).  Synchronises. */
+int tdks_density(tdks_ctx *ctx, int inst, double *rho_out);
+
+/* Diagnostics (not on the timed path). */
+
+/* v_Hxc in use for the next step of instance inst, HOST out [N3][N2][N1]. */
+int tdks_vhxc(tdks_ctx *ctx, int inst, double *out);
+
+/* Local potential v_loc of instance inst, HOST out [N3][N2][N1]. */
+int tdks_vloc(tdks_ctx *ctx, int inst, double *out);
+
+/* Present orbitals of instance inst as complex128 [k][band][i3][i2][i1]. */
+int tdks_get_orbitals(tdks_ctx *ctx, int inst, void *u_out, int where);
+
+/* Norms sum_r |u|^2 dV (FP64) of instance inst, HOST out [k][band]. */
+int tdks_norms(tdks_ctx *ctx, int inst, double *out);
+
+/* One application hw = h_kappa w (Eq. 2) for every k and band of instance
+ * inst, with kappa = k + A (A HOST [3]) and the present v_Hxc; w and hw are
+ * complex128 [k][band][i3][i2][i1] in `where` memory.  Uses the propagation
+ * kernel's stencil, potential and projector code path. */
+int tdks_apply_h(tdks_ctx *ctx, int inst, const void *w, void *hw, const double *A, int where);
+
+/* Tiling actually used by the first grid shape: threads per workgroup, length of
+ * the z-column segment each thread owns, bands and k-points per workgroup, and
+ * the number of workgroups per step (all shapes).  Outputs may be NULL. */
+int tdks_tiling(tdks_ctx *ctx, int *block, int *zl, int *bands_per_group, int *k_per_group,
+                int *n_groups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDKS_H */

@@ -1,0 +1,94 @@
+// Internal structures shared by the host runtime (tdks_runtime.cpp) and the
+// device kernels (tdks_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdks {
+
+constexpr int kMaxAtoms = 64;
+constexpr int kMaxGridDim = 32;   // N_d <= 32 (DFT lines held in registers; packed j_d + N_d < 256)
+constexpr int kMaxPoints = 8192;  // N1 N2 N3 <= 8192 (one orbital per workgroup in LDS)
+constexpr int kTaskLen = 128;     // projector entries per projection task (two per lane)
+
+// Per-instance data visible to the kernels (lives in device memory).
+struct DevInst {
+    int N[3];
+    int ng;
+    int nk, nb, nat;
+    int nonorth;        // lattice not orthogonal: mixed second derivatives present
+    int ntask;          // projection tasks (atom-major entry ranges)
+    double dV, omega;
+    double lat[3][3];   // rows a_d
+    double hv[3][3];    // rows a_d / N_d (grid step vectors)
+    double c[3][3];     // rows c_d = N_d b_d / (2 pi): grad = sum_d c_d d/ds_d
+    double g[3][3];     // metric g_de = c_d . c_e
+    void *u;            // orbitals [nk][nb][ng], complex R (float2 / double2)
+    const void *vtot;   // v_loc + v_Hxc in R precision [ng]
+    const double *kcart;  // [nk][3]
+    const double *kw;     // [nk]
+    const double *occ;    // [nb]
+    // projectors (k-independent tables, shared between identical cells)
+    const uint32_t *ent_pack;  // atom-major entries: j1+N1 | j2+N2 << 8 | j3+N3 << 16 | atom << 24
+    const double *ent_g;       // radial factor g(d) of each atom-major entry
+    const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
+    const uint32_t *pt_pack;   // point-major copy of ent_pack
+    const double *pt_g;        // point-major copy of ent_g
+    const int2 *task;          // [ntask] {first entry, atom | count << 8}
+    const int *atom_task;      // [nat+1] first task of each atom
+    const double *atom_tau;    // [nat][3] Cartesian positions
+    const double *atom_par;    // [nat][4] Es, Ep, Ns, Np
+    // per-step outputs of the propagation kernel
+    double *rho_part;   // [nslot][ng] partial densities (one slot per work item)
+    double *j_part;     // [nslot][4] partial currents
+    int nslot;
+    int pad_;
+};
+
+// One workgroup's share: bands [b0, b0+nb) of k-points [k0, k0+nk) of an instance.
+struct WorkItem {
+    int inst, k0, nk, b0, nb, slot;
+};
+
+// Built (column-segment length ZL, max threads per workgroup) pairs of the propagation
+// kernel.  N3 must be a multiple of ZL; the block is N1 N2 (N3 / ZL) threads rounded up to 64.
+#define TDKS_PROPAGATE_CONFIGS(X) \
+    X(2, 512) X(3, 512) X(4, 512) X(6, 512) X(8, 512) X(12, 512) X(16, 512) \
+    X(4, 1024) X(8, 1024) X(10, 1024)
+
+enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2 };
+
+struct PropArgs {
+    const DevInst *insts;
+    const WorkItem *work;
+    const double *A_tab;   // [*][2][3]
+    const int *step_ctr;   // A_tab row to use
+    double dt;
+    int mode;
+    int ng_max;            // largest grid of the launch (sizes the LDS orbital buffer)
+    int nmaxd;             // largest N_d of the launch (phase tables)
+    int nat_max;           // most atoms of an instance in the launch
+    int ntask_max;         // most projection tasks of an instance in the launch
+    const void *apply_in;  // MODE_APPLY: input orbitals [nk][nb][ng] complex R of instance
+    void *apply_out;       // MODE_APPLY: output
+};
+
+// Host-side launchers implemented in tdks_kernels.hip.
+hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int ppt,
+                            int nonorth, hipStream_t s);
+size_t propagate_lds_bytes(int fp64, const PropArgs &a, int block);
+bool propagate_config_ok(int block, int ppt);
+hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
+                         double *jout, int jstride, const int *rec_ctr, hipStream_t s);
+hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const double *rho,
+                      const double *vloc, double *vhxc, void *vtot, int fp64, hipStream_t s);
+hipError_t launch_vtot(const DevInst *insts, int inst0, int n, int ng_max, const double *vloc,
+                       const double *vhxc, void *vtot, int fp64, hipStream_t s);
+hipError_t launch_advance(int *ctrs, int n, hipStream_t s);
+hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
+hipError_t launch_convert_in(const double *src, void *dst, size_t n_complex, int fp64, hipStream_t s);
+hipError_t launch_convert_out(const void *src, double *dst, size_t n_complex, int fp64, hipStream_t s);
+hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, double *out, hipStream_t s);
+
+}  // namespace tdks

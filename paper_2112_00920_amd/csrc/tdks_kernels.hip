@@ -1,0 +1,313 @@
+// HIP kernels for CDNA4 (gfx950) around the propagation kernel: dispatch of the
+// propagation variants, deterministic FP64 reductions, Hartree + LDA, utilities.
+#include "tdks_propagate.h"
+
+namespace tdks {
+
+hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, hipStream_t);
+hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, hipStream_t);
+
+size_t propagate_lds_bytes(int fp64, const PropArgs &a, int block) {
+    return propagate_lds_bytes_inl(fp64, a, block);
+}
+
+bool propagate_config_ok(int block, int zl) {
+    if (block < 64 || block > 1024 || (block & 63)) return false;
+#define TDKS_OK_CASE(Z, M) if (zl == Z && block <= M) return true;
+    TDKS_PROPAGATE_CONFIGS(TDKS_OK_CASE)
+#undef TDKS_OK_CASE
+    return false;
+}
+
+hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl,
+                            int nonorth, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, s)
+                             : launch_propagate_f64_orth(a, n_items, block, zl, s);
+    return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, s)
+                   : launch_propagate_f32_orth(a, n_items, block, zl, s);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reduction of the per-workgroup partials (fixed slot order).
+__global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0, int ng_max,
+                                                double *rho, double *jout, int jstride,
+                                                const int *rec_ctr) {
+    const int inst = inst0 + blockIdx.y;
+    const DevInst &I = insts[inst];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < I.ng) {
+        double s = 0.0;
+        for (int q = 0; q < I.nslot; ++q) s += I.rho_part[size_t(q) * I.ng + p];
+        rho[size_t(inst) * ng_max + p] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 3) {
+        double s = 0.0;
+        for (int q = 0; q < I.nslot; ++q) s += I.j_part[4 * q + threadIdx.x];
+        const int rec = rec_ctr ? *rec_ctr : 0;
+        jout[(size_t(inst) * jstride + rec) * 3 + threadIdx.x] = -s / I.omega;
+    }
+}
+
+hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
+                         double *jout, int jstride, const int *rec_ctr, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((ng_max + 255) / 256, n);
+    hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, insts, inst0, ng_max, rho, jout, jstride,
+                       rec_ctr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Hartree + LDA, one workgroup per instance.  Poisson: rho(G) by a separable
+// discrete Fourier transform (each line of N_d <= 32 points held in registers,
+// twiddles from sincospi), v_H(G) = 4 pi rho(G) / |G|^2 with G = 0 and the
+// Nyquist planes zeroed, inverse transform.  Exchange: Slater; correlation:
+// Perdew-Zunger 81 (unpolarised).
+__device__ double lda_vxc(double rho) {
+    if (!(rho > 1e-30)) return 0.0;
+    const double pi = 3.141592653589793;
+    const double vx = -cbrt(3.0 * rho / pi);
+    const double rs = cbrt(3.0 / (4.0 * pi * rho));
+    double vc;
+    if (rs >= 1.0) {
+        const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+        const double sq = sqrt(rs);
+        const double den = 1.0 + b1 * sq + b2 * rs;
+        vc = g / den * (1.0 + 7.0 / 6.0 * b1 * sq + 4.0 / 3.0 * b2 * rs) / den;
+    } else {
+        const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+        const double l = log(rs);
+        vc = A * l + (B - A / 3.0) + 2.0 / 3.0 * C * rs * l + (2.0 * D - C) / 3.0 * rs;
+    }
+    return vx + vc;
+}
+
+__device__ void dft_pass(double2 *X, const double2 *tw, int n, int stride, int nlines,
+                         int inner, int ninner_stride, bool inverse) {
+    // lines: start = (l % inner) + (l / inner) * ninner_stride, element i at start + i*stride
+    for (int l = threadIdx.x; l < nlines; l += blockDim.x) {
+        const int start = (l % inner) + (l / inner) * ninner_stride;
+        double2 line[kMaxGridDim];
+#pragma unroll
+        for (int i = 0; i < kMaxGridDim; ++i)
+            if (i < n) line[i] = X[start + i * stride];
+        for (int m = 0; m < n; ++m) {
+            double sx = 0.0, sy = 0.0;
+            int q = 0;
+#pragma unroll
+            for (int i = 0; i < kMaxGridDim; ++i) {
+                if (i < n) {
+                    double2 t = tw[q];
+                    double ty = inverse ? -t.y : t.y;
+                    sx += line[i].x * t.x - line[i].y * ty;
+                    sy += line[i].x * ty + line[i].y * t.x;
+                    q += m;
+                    if (q >= n) q -= n;
+                }
+            }
+            X[start + m * stride] = make_double2(sx, sy);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_hxc(const DevInst *insts, int inst0, int ng_max,
+                                             const double *rho, const double *vloc, double *vhxc,
+                                             R *vtot) {
+    extern __shared__ __align__(16) char smem[];
+    const int inst = inst0 + blockIdx.x;
+    const DevInst &I = insts[inst];
+    const int ng = I.ng, N0 = I.N[0], N1 = I.N[1], N2 = I.N[2];
+    double2 *X = reinterpret_cast<double2 *>(smem);
+    double2 *tw = X + ng_max;  // [3][kMaxGridDim] e^{-2 pi i q / N_d}
+    const size_t base = size_t(inst) * ng_max;
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) X[p] = make_double2(rho[base + p], 0.0);
+    for (int idx = threadIdx.x; idx < 3 * kMaxGridDim; idx += blockDim.x) {
+        int d = idx / kMaxGridDim, q = idx % kMaxGridDim;
+        int n = I.N[d];
+        double s, c;
+        sincospi(2.0 * q / n, &s, &c);
+        tw[idx] = make_double2(c, -s);
+    }
+    __syncthreads();
+    // forward transform along i1, i2, i3
+    dft_pass(X, tw, N0, 1, N1 * N2, 1, N0, false);
+    __syncthreads();
+    dft_pass(X, tw + kMaxGridDim, N1, N0, N0 * N2, N0, N0 * N1, false);
+    __syncthreads();
+    dft_pass(X, tw + 2 * kMaxGridDim, N2, N0 * N1, N0 * N1, N0 * N1, 0, false);
+    __syncthreads();
+    const double two_pi = 6.283185307179586;
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+        const int m0 = p % N0, m1 = (p / N0) % N1, m2 = p / (N0 * N1);
+        const int s0 = m0 < (N0 + 1) / 2 ? m0 : m0 - N0;
+        const int s1 = m1 < (N1 + 1) / 2 ? m1 : m1 - N1;
+        const int s2 = m2 < (N2 + 1) / 2 ? m2 : m2 - N2;
+        const bool nyq = ((N0 % 2 == 0) && s0 == -N0 / 2) || ((N1 % 2 == 0) && s1 == -N1 / 2) ||
+                         ((N2 % 2 == 0) && s2 == -N2 / 2);
+        double G[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            G[q] = two_pi * (s0 * I.c[0][q] / N0 + s1 * I.c[1][q] / N1 + s2 * I.c[2][q] / N2);
+        const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+        double2 v = X[p];
+        if (nyq || (s0 == 0 && s1 == 0 && s2 == 0)) {
+            v = make_double2(0.0, 0.0);
+        } else {
+            const double f = 4.0 * 3.141592653589793 / g2;
+            v.x *= f;
+            v.y *= f;
+        }
+        X[p] = v;
+    }
+    __syncthreads();
+    dft_pass(X, tw, N0, 1, N1 * N2, 1, N0, true);
+    __syncthreads();
+    dft_pass(X, tw + kMaxGridDim, N1, N0, N0 * N2, N0, N0 * N1, true);
+    __syncthreads();
+    dft_pass(X, tw + 2 * kMaxGridDim, N2, N0 * N1, N0 * N1, N0 * N1, 0, true);
+    __syncthreads();
+    for (int p = threadIdx.x; p < ng; p += blockDim.x) {
+        const double vh = X[p].x / ng;
+        const double v = vh + lda_vxc(rho[base + p]);
+        vhxc[base + p] = v;
+        vtot[base + p] = R(vloc[base + p] + v);
+    }
+}
+
+hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const double *rho,
+                      const double *vloc, double *vhxc, void *vtot, int fp64, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const size_t lds = 16 * size_t(ng_max) + 16 * 3 * kMaxGridDim;
+    if (fp64) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_hxc<double>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_hxc<double>, dim3(n), dim3(256), lds, s, insts, inst0, ng_max, rho,
+                           vloc, vhxc, reinterpret_cast<double *>(vtot));
+    } else {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_hxc<float>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_hxc<float>, dim3(n), dim3(256), lds, s, insts, inst0, ng_max, rho,
+                           vloc, vhxc, reinterpret_cast<float *>(vtot));
+    }
+    return hipGetLastError();
+}
+
+template <typename R>
+__global__ void k_vtot(const DevInst *insts, int inst0, int ng_max, const double *vloc,
+                       const double *vhxc, R *vtot) {
+    const int inst = inst0 + blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < insts[inst].ng) {
+        const size_t o = size_t(inst) * ng_max + p;
+        vtot[o] = R(vloc[o] + vhxc[o]);
+    }
+}
+
+hipError_t launch_vtot(const DevInst *insts, int inst0, int n, int ng_max, const double *vloc,
+                       const double *vhxc, void *vtot, int fp64, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((ng_max + 255) / 256, n);
+    if (fp64)
+        hipLaunchKernelGGL(k_vtot<double>, grid, dim3(256), 0, s, insts, inst0, ng_max, vloc, vhxc,
+                           reinterpret_cast<double *>(vtot));
+    else
+        hipLaunchKernelGGL(k_vtot<float>, grid, dim3(256), 0, s, insts, inst0, ng_max, vloc, vhxc,
+                           reinterpret_cast<float *>(vtot));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// small utility kernels (graph-capturable: no memset nodes)
+__global__ void k_advance(int *ctrs, int n) {
+    if (threadIdx.x < n) ctrs[threadIdx.x] += 1;
+}
+hipError_t launch_advance(int *ctrs, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctrs, n);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_int(int *p, int v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+template <typename C>
+__global__ void k_convert_in(const double2 *src, C *dst, size_t n) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+         i += size_t(gridDim.x) * blockDim.x) {
+        double2 v = src[i];
+        C o;
+        o.x = decltype(o.x)(v.x);
+        o.y = decltype(o.y)(v.y);
+        dst[i] = o;
+    }
+}
+template <typename C>
+__global__ void k_convert_out(const C *src, double2 *dst, size_t n) {
+    for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n;
+         i += size_t(gridDim.x) * blockDim.x) {
+        C v = src[i];
+        dst[i] = make_double2(double(v.x), double(v.y));
+    }
+}
+hipError_t launch_convert_in(const double *src, void *dst, size_t n, int fp64, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = int((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (fp64)
+        hipLaunchKernelGGL(k_convert_in<double2>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const double2 *>(src), reinterpret_cast<double2 *>(dst), n);
+    else
+        hipLaunchKernelGGL(k_convert_in<float2>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const double2 *>(src), reinterpret_cast<float2 *>(dst), n);
+    return hipGetLastError();
+}
+hipError_t launch_convert_out(const void *src, double *dst, size_t n, int fp64, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int blocks = int((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (fp64)
+        hipLaunchKernelGGL(k_convert_out<double2>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const double2 *>(src), reinterpret_cast<double2 *>(dst), n);
+    else
+        hipLaunchKernelGGL(k_convert_out<float2>, dim3(blocks), dim3(256), 0, s,
+                           reinterpret_cast<const float2 *>(src), reinterpret_cast<double2 *>(dst), n);
+    return hipGetLastError();
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_norms(const C *u, int ng, double dV, double *out) {
+    __shared__ double red[4];
+    const C *o = u + size_t(blockIdx.x) * ng;
+    double s = 0.0;
+    for (int p = threadIdx.x; p < ng; p += 256) {
+        C v = o[p];
+        s += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * dV;
+}
+hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, double *out,
+                        hipStream_t s) {
+    if (n_orb <= 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_norms<double2>, dim3(n_orb), dim3(256), 0, s,
+                           reinterpret_cast<const double2 *>(u), ng, dV, out);
+    else
+        hipLaunchKernelGGL(k_norms<float2>, dim3(n_orb), dim3(256), 0, s,
+                           reinterpret_cast<const float2 *>(u), ng, dV, out);
+    return hipGetLastError();
+}
+
+}  // namespace tdks

@@ -1,0 +1,29 @@
+#define REAL float
+#define NONORTH_FLAG false
+#define LAUNCH_NAME launch_propagate_f32_orth
+// Instantiations of k_propagate for one arithmetic type and cell kind (split so the
+// four variants compile in parallel).
+#include "tdks_propagate.h"
+
+namespace tdks {
+
+template <int ZL, int MAXT>
+static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    auto kern = k_propagate<REAL, ZL, NONORTH_FLAG, MAXT>;
+    const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, a, block);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t LAUNCH_NAME(const PropArgs &a, int n_items, int block, int zl, hipStream_t s) {
+#define TDKS_CASE(Z, M) \
+    if (zl == Z && block <= M) return launch_zl<Z, M>(a, n_items, block, s);
+    TDKS_PROPAGATE_CONFIGS(TDKS_CASE)
+#undef TDKS_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tdks

@@ -1,0 +1,1009 @@
+// Host runtime behind the tdks C ABI (include/tdks.h): instance set-up (geometry,
+// local potential, projector support tables, k tables), device layout, work lists,
+// per-step HIP graphs, and read-out.
+//
+// Set-up arithmetic follows the model stated in tdks.h: grid r(i) = sum_d (i_d/N_d) a_d,
+// reciprocal rows b_d with a_d . b_e = 2 pi delta_de, gradient = sum_d c_d d/ds_d with
+// c_d = N_d b_d / (2 pi), metric g_de = c_d . c_e; Gaussian local potential summed over all
+// lattice images within 15 widths; s + p Kleinman-Bylander projectors
+// f_s = N_s g, f_p = N_p d g, g = max(0, exp(-d^2/2rc^2) - exp(-Rc^2/2rc^2)).
+#include "tdks_internal.h"
+
+#include "../../include/tdks.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace tdks;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(TDKS_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                              \
+    } while (0)
+
+struct TableSet {
+    std::vector<uint32_t> ent_pack, pt_pack;
+    std::vector<double> ent_g, pt_g;
+    std::vector<int> pt_ptr, atom_task;
+    std::vector<int2> task;
+    std::vector<double> atom_tau, atom_par;
+    int nat = 0;
+    // device copies
+    uint32_t *d_ent_pack = nullptr, *d_pt_pack = nullptr;
+    double *d_ent_g = nullptr, *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
+    int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
+    int2 *d_task = nullptr;
+};
+
+struct InstHost {
+    int N[3];
+    int ng;
+    int nk, nb, nat;
+    int group;
+    bool nonorth;
+    double lat[3][3], B[3][3], c[3][3], g[3][3], hv[3][3];
+    double omega, dV;
+    std::vector<double> kcart, kw, occ, vloc, vhxc_frozen;
+    int table = -1;
+    int cls = -1;
+    int wbeg = 0, wend = 0;  // work items (global indices) of this instance
+    int nslot = 0;
+    void *d_u = nullptr;
+    double *d_kcart = nullptr, *d_kw = nullptr, *d_occ = nullptr;
+    double *d_rho_part = nullptr, *d_j_part = nullptr;
+    bool loaded = false;
+};
+
+struct ShapeClass {
+    int N[3];
+    bool nonorth;
+    int zl = 0, block = 0;
+    int wbeg = 0, wend = 0;
+    int ng_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
+};
+
+}  // namespace
+
+struct tdks_ctx {
+    tdks_options opt;
+    int fp64 = 1;
+    int n_inst = 0;
+    std::vector<InstHost> inst;
+    std::vector<TableSet> tables;
+    std::vector<ShapeClass> classes;
+    std::vector<WorkItem> work;
+    std::vector<int> groups;  // sorted distinct group ids
+    int ng_max = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t caller = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_acopy = nullptr;
+    // device buffers
+    DevInst *d_insts = nullptr;
+    WorkItem *d_work = nullptr;
+    double *d_rho = nullptr, *d_vloc = nullptr, *d_vhxc = nullptr;
+    void *d_vtot = nullptr;
+    double *d_trace = nullptr;
+    size_t trace_cap = 0;  // records per instance
+    double *d_A = nullptr;
+    size_t A_cap = 0;
+    double *h_A = nullptr;  // pinned staging
+    int *d_ctrs = nullptr;  // [0] A row, [1] record index, [2] always 0
+    double *d_jpre = nullptr, *d_jobs = nullptr, *d_Aobs = nullptr;
+    std::vector<double> jpre;
+    int steps_done = 0;
+    hipGraphExec_t g_chunk = nullptr, g_one = nullptr;
+    int chunk = 16;
+    std::vector<void *> allocs;
+
+    void *alloc(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        void *p = nullptr;
+        if (opt.alloc) {
+            p = opt.alloc(bytes, opt.alloc_user);
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+        }
+        if (p) allocs.push_back(p);
+        return p;
+    }
+    void release(void *p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        if (opt.free)
+            opt.free(p, opt.alloc_user);
+        else
+            (void)hipFree(p);
+    }
+    void drop_graphs() {
+        if (g_chunk) (void)hipGraphExecDestroy(g_chunk);
+        if (g_one) (void)hipGraphExecDestroy(g_one);
+        g_chunk = g_one = nullptr;
+    }
+};
+
+namespace {
+
+void inv3(const double a[3][3], double out[3][3], double &det) {
+    det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+          a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+          a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+    const double id = 1.0 / det;
+    out[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) * id;
+    out[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) * id;
+    out[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) * id;
+    out[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) * id;
+    out[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
+    out[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;
+    out[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) * id;
+    out[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) * id;
+    out[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
+}
+
+const double kPi = 3.14159265358979323846;
+
+// grid point r(i) = sum_d (i_d / N_d) a_d for flat index p = i0 + N0 (i1 + N1 i2)
+void point(const InstHost &I, int p, double r[3]) {
+    const int i0 = p % I.N[0], i1 = (p / I.N[0]) % I.N[1], i2 = p / (I.N[0] * I.N[1]);
+    for (int q = 0; q < 3; ++q)
+        r[q] = double(i0) / I.N[0] * I.lat[0][q] + double(i1) / I.N[1] * I.lat[1][q] +
+               double(i2) / I.N[2] * I.lat[2][q];
+}
+
+int build_geometry(InstHost &I, const tdks_instance_desc &d) {
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) I.lat[a][b] = d.lattice[a][b];
+    for (int q = 0; q < 3; ++q) I.N[q] = d.grid[q];
+    for (int q = 0; q < 3; ++q)
+        if (I.N[q] < 4 || I.N[q] > kMaxGridDim)
+            return fail(TDKS_E_UNSUPPORTED, "grid dimension %d = %d outside [4, %d]", q, I.N[q], kMaxGridDim);
+    I.ng = I.N[0] * I.N[1] * I.N[2];
+    if (I.ng > kMaxPoints) return fail(TDKS_E_UNSUPPORTED, "grid of %d points exceeds %d", I.ng, kMaxPoints);
+    double inv[3][3], det;
+    inv3(I.lat, inv, det);
+    if (!(std::fabs(det) > 1e-12)) return fail(TDKS_E_ARG, "singular lattice");
+    I.omega = std::fabs(det);
+    I.dV = I.omega / I.ng;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) I.B[a][b] = 2.0 * kPi * inv[b][a];  // rows b_a
+    for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 3; ++q) {
+            I.c[a][q] = I.N[a] * I.B[a][q] / (2.0 * kPi);
+            I.hv[a][q] = I.lat[a][q] / I.N[a];
+        }
+    I.nonorth = false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            I.g[a][b] = I.c[a][0] * I.c[b][0] + I.c[a][1] * I.c[b][1] + I.c[a][2] * I.c[b][2];
+            if (a != b && I.g[a][b] != 0.0) I.nonorth = true;
+        }
+    return TDKS_OK;
+}
+
+int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSet &T) {
+    const int nat = d.n_atoms;
+    T.nat = nat;
+    T.atom_tau.assign(3 * nat, 0.0);
+    T.atom_par.assign(4 * nat, 0.0);
+    for (int a = 0; a < nat; ++a) {
+        for (int q = 0; q < 3; ++q)
+            T.atom_tau[3 * a + q] = d.atom_frac[3 * a + 0] * I.lat[0][q] +
+                                    d.atom_frac[3 * a + 1] * I.lat[1][q] +
+                                    d.atom_frac[3 * a + 2] * I.lat[2][q];
+        const tdks_species &sp = d.species[d.atom_species[a]];
+        T.atom_par[4 * a + 0] = sp.Es;
+        T.atom_par[4 * a + 1] = sp.Ep;
+        T.atom_par[4 * a + 2] = std::pow(std::pow(kPi, 1.5) * sp.rc * sp.rc * sp.rc, -0.5);
+        T.atom_par[4 * a + 3] = std::pow(std::pow(kPi, 1.5) * std::pow(sp.rc, 5) / 2.0, -0.5);
+    }
+    // local potential: every image within 15 widths
+    I.vloc.assign(I.ng, 0.0);
+    std::vector<double> r(3 * I.ng);
+    for (int p = 0; p < I.ng; ++p) point(I, p, &r[3 * p]);
+    for (int a = 0; a < nat; ++a) {
+        const tdks_species &sp = d.species[d.atom_species[a]];
+        const double rcut = 15.0 * sp.w;
+        int nmax[3];
+        for (int q = 0; q < 3; ++q) {
+            const double bn = std::sqrt(I.B[q][0] * I.B[q][0] + I.B[q][1] * I.B[q][1] + I.B[q][2] * I.B[q][2]);
+            nmax[q] = int(std::ceil(rcut * bn / (2.0 * kPi))) + 1;
+        }
+        const double inv2w2 = 1.0 / (2.0 * sp.w * sp.w);
+        for (int n0 = -nmax[0]; n0 <= nmax[0]; ++n0)
+            for (int n1 = -nmax[1]; n1 <= nmax[1]; ++n1)
+                for (int n2 = -nmax[2]; n2 <= nmax[2]; ++n2) {
+                    double c[3];
+                    for (int q = 0; q < 3; ++q)
+                        c[q] = T.atom_tau[3 * a + q] + n0 * I.lat[0][q] + n1 * I.lat[1][q] + n2 * I.lat[2][q];
+                    for (int p = 0; p < I.ng; ++p) {
+                        const double x = r[3 * p] - c[0], y = r[3 * p + 1] - c[1], z = r[3 * p + 2] - c[2];
+                        const double d2 = x * x + y * y + z * z;
+                        if (d2 < rcut * rcut) I.vloc[p] += sp.D * std::exp(-d2 * inv2w2);
+                    }
+                }
+    }
+    // projector support: points within Rc of exactly one image of each atom
+    struct Ent { int p; uint32_t pack; double g; };
+    std::vector<std::vector<Ent>> per_atom(nat);
+    for (int a = 0; a < nat; ++a) {
+        const tdks_species &sp = d.species[d.atom_species[a]];
+        if (!(sp.Rc > 0.0) || !(sp.rc > 0.0)) return fail(TDKS_E_ARG, "species radii must be positive");
+        const double gcut = std::exp(-sp.Rc * sp.Rc / (2.0 * sp.rc * sp.rc));
+        std::vector<int> hits(I.ng, 0);
+        for (int n0 = -2; n0 <= 2; ++n0)
+            for (int n1 = -2; n1 <= 2; ++n1)
+                for (int n2 = -2; n2 <= 2; ++n2) {
+                    double c[3];
+                    for (int q = 0; q < 3; ++q)
+                        c[q] = T.atom_tau[3 * a + q] + n0 * I.lat[0][q] + n1 * I.lat[1][q] + n2 * I.lat[2][q];
+                    for (int p = 0; p < I.ng; ++p) {
+                        const double x = r[3 * p] - c[0], y = r[3 * p + 1] - c[1], z = r[3 * p + 2] - c[2];
+                        const double d2 = x * x + y * y + z * z;
+                        if (!(d2 < sp.Rc * sp.Rc)) continue;
+                        if (++hits[p] > 1)
+                            return fail(TDKS_E_ARG, "atom %d: projector radius %.3f reaches two images of the "
+                                        "same atom (must be below half the shortest lattice translation)", a, sp.Rc);
+                        const int i0 = p % I.N[0], i1 = (p / I.N[0]) % I.N[1], i2 = p / (I.N[0] * I.N[1]);
+                        const int j0 = i0 - n0 * I.N[0], j1 = i1 - n1 * I.N[1], j2 = i2 - n2 * I.N[2];
+                        const int u0 = j0 + I.N[0], u1 = j1 + I.N[1], u2 = j2 + I.N[2];
+                        if (u0 < 0 || u0 >= 3 * I.N[0] || u1 < 0 || u1 >= 3 * I.N[1] || u2 < 0 || u2 >= 3 * I.N[2])
+                            return fail(TDKS_E_ARG, "atom %d: projector support outside the neighbouring cells", a);
+                        const double g = std::max(0.0, std::exp(-d2 / (2.0 * sp.rc * sp.rc)) - gcut);
+                        const uint32_t pack = uint32_t(u0) | (uint32_t(u1) << 8) | (uint32_t(u2) << 16) |
+                                              (uint32_t(a) << 24);
+                        per_atom[a].push_back({p, pack, g});
+                    }
+                }
+        std::sort(per_atom[a].begin(), per_atom[a].end(), [](const Ent &x, const Ent &y) { return x.p < y.p; });
+    }
+    T.ent_pack.clear();
+    T.ent_g.clear();
+    T.task.clear();
+    T.atom_task.assign(nat + 1, 0);
+    std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
+    for (int a = 0; a < nat; ++a) {
+        T.atom_task[a] = int(T.task.size());
+        const int base = int(T.ent_pack.size());
+        const int cnt = int(per_atom[a].size());
+        if (cnt == 0) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
+        for (const Ent &e : per_atom[a]) {
+            T.ent_pack.push_back(e.pack);
+            T.ent_g.push_back(e.g);
+            per_point[e.p].push_back({e.pack, e.g});
+        }
+        for (int s = 0; s < cnt; s += kTaskLen) {
+            const int len = std::min(kTaskLen, cnt - s);
+            T.task.push_back(make_int2(base + s, a | (len << 8)));
+        }
+    }
+    T.atom_task[nat] = int(T.task.size());
+    T.pt_ptr.assign(I.ng + 1, 0);
+    T.pt_pack.clear();
+    T.pt_g.clear();
+    for (int p = 0; p < I.ng; ++p) {
+        T.pt_ptr[p] = int(T.pt_pack.size());
+        for (auto &e : per_point[p]) {
+            T.pt_pack.push_back(e.first);
+            T.pt_g.push_back(e.second);
+        }
+    }
+    T.pt_ptr[I.ng] = int(T.pt_pack.size());
+    return TDKS_OK;
+}
+
+std::string table_key(const tdks_instance_desc &d) {
+    std::string k;
+    auto add = [&](const void *p, size_t n) { k.append(reinterpret_cast<const char *>(p), n); };
+    add(d.lattice, sizeof(d.lattice));
+    add(d.grid, sizeof(d.grid));
+    add(&d.n_atoms, sizeof(int));
+    add(d.atom_frac, sizeof(double) * 3 * d.n_atoms);
+    for (int a = 0; a < d.n_atoms; ++a) add(&d.species[d.atom_species[a]], sizeof(tdks_species));
+    return k;
+}
+
+template <typename T>
+int upload(tdks_ctx *c, T **dst, const std::vector<T> &src) {
+    *dst = static_cast<T *>(c->alloc(sizeof(T) * std::max<size_t>(src.size(), 1)));
+    if (!*dst) return fail(TDKS_E_OOM, "device allocation of %zu bytes failed", sizeof(T) * src.size());
+    if (!src.empty()) HIPCHK(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return TDKS_OK;
+}
+
+#define CHK(expr)                     \
+    do {                              \
+        int r_ = (expr);              \
+        if (r_ != TDKS_OK) return r_; \
+    } while (0)
+
+// choose the column-segment length and block for one grid shape
+bool choose_tiling(const int N[3], int fp64, int want_block, int &zl, int &block) {
+    static const int zls[] = {2, 3, 4, 6, 8, 10, 12, 16};
+    const int target = fp64 ? 4 : 8;
+    int best = -1, best_cost = 1 << 30;
+    for (int z : zls) {
+        if (N[2] % z) continue;
+        int b = N[0] * N[1] * (N[2] / z);
+        b = (b + 63) / 64 * 64;
+        if (!propagate_config_ok(b, z)) continue;
+        int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
+        if (want_block > 0) cost = std::abs(b - want_block) * 16 + std::abs(z - target);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = z;
+            block = b;
+        }
+    }
+    if (best < 0) return false;
+    zl = best;
+    return true;
+}
+
+int sync_in(tdks_ctx *c) {
+    if (c->caller != c->stream) {
+        HIPCHK(hipEventRecord(c->ev_in, c->caller));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+    }
+    return TDKS_OK;
+}
+int sync_out(tdks_ctx *c) {
+    if (c->caller != c->stream) {
+        HIPCHK(hipEventRecord(c->ev_out, c->stream));
+        HIPCHK(hipStreamWaitEvent(c->caller, c->ev_out, 0));
+    }
+    return TDKS_OK;
+}
+
+PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A, const int *ctr) {
+    PropArgs a;
+    a.insts = c->d_insts;
+    a.work = c->d_work;
+    a.A_tab = A;
+    a.step_ctr = ctr;
+    a.dt = c->opt.dt;
+    a.mode = mode;
+    a.ng_max = S.ng_max;
+    a.nmaxd = S.nmaxd;
+    a.nat_max = S.nat_max;
+    a.ntask_max = S.ntask_max;
+    a.apply_in = nullptr;
+    a.apply_out = nullptr;
+    return a;
+}
+
+// enqueue one time step of every instance (graph-capturable)
+int enqueue_step(tdks_ctx *c) {
+    for (const ShapeClass &S : c->classes) {
+        PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
+        a.work = c->d_work + S.wbeg;
+        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.nonorth, c->stream));
+    }
+    HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
+                         c->d_ctrs + 1, c->stream));
+    if (c->opt.hxc_mode == TDKS_HXC_SCF)
+        HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot,
+                          c->fp64, c->stream));
+    HIPCHK(launch_advance(c->d_ctrs, 2, c->stream));
+    return TDKS_OK;
+}
+
+int build_graph(tdks_ctx *c, int nsteps, hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int rc = TDKS_OK;
+    for (int s = 0; s < nsteps && rc == TDKS_OK; ++s) rc = enqueue_step(c);
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (rc != TDKS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(TDKS_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(TDKS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    return TDKS_OK;
+}
+
+int ensure_trace(tdks_ctx *c, size_t need) {
+    if (need <= c->trace_cap) return TDKS_OK;
+    size_t cap = std::max<size_t>(need, std::max<size_t>(2 * c->trace_cap, 1024));
+    double *nt = static_cast<double *>(c->alloc(sizeof(double) * 3 * cap * c->n_inst));
+    if (!nt) return fail(TDKS_E_OOM, "trace allocation failed");
+    if (c->d_trace && c->steps_done > 0) {
+        HIPCHK(hipMemcpy2DAsync(nt, sizeof(double) * 3 * cap, c->d_trace, sizeof(double) * 3 * c->trace_cap,
+                                sizeof(double) * 3 * c->steps_done, c->n_inst, hipMemcpyDeviceToDevice,
+                                c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->release(c->d_trace);
+    c->d_trace = nt;
+    c->trace_cap = cap;
+    c->drop_graphs();
+    return TDKS_OK;
+}
+
+int ensure_A(tdks_ctx *c, size_t n) {
+    if (n <= c->A_cap) return TDKS_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    size_t cap = std::max<size_t>(n, std::max<size_t>(2 * c->A_cap, 1024));
+    double *na = static_cast<double *>(c->alloc(sizeof(double) * 6 * cap));
+    if (!na) return fail(TDKS_E_OOM, "A table allocation failed");
+    c->release(c->d_A);
+    c->d_A = na;
+    if (c->h_A) (void)hipHostFree(c->h_A);
+    c->h_A = nullptr;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c->h_A), sizeof(double) * 6 * cap, hipHostMallocDefault));
+    c->A_cap = cap;
+    c->drop_graphs();
+    return TDKS_OK;
+}
+
+int check_inst(tdks_ctx *c, int i) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    if (i < 0 || i >= c->n_inst) return fail(TDKS_E_ARG, "instance %d out of range [0, %d)", i, c->n_inst);
+    return TDKS_OK;
+}
+
+size_t orb_bytes(const tdks_ctx *c, const InstHost &I) {
+    return size_t(I.nk) * I.nb * I.ng * (c->fp64 ? 16 : 8);
+}
+
+// observe: current (and density) of instance range for given A; writes d_jobs or d_jpre
+int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jdst) {
+    double h[6] = {A[0], A[1], A[2], A[0], A[1], A[2]};
+    HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    for (const ShapeClass &S : c->classes) {
+        int wb = S.wend, we = S.wbeg;
+        for (int i = i_first; i <= i_last; ++i) {
+            const InstHost &I = c->inst[i];
+            if (I.cls != int(&S - &c->classes[0])) continue;
+            wb = std::min(wb, I.wbeg);
+            we = std::max(we, I.wend);
+        }
+        if (we <= wb) continue;
+        PropArgs a = class_args(c, S, MODE_OBSERVE, c->d_Aobs, c->d_ctrs + 2);
+        a.work = c->d_work + wb;
+        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.nonorth, c->stream));
+    }
+    HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
+                         c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TDKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tdks_default_options(tdks_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = TDKS_FP64;
+    opt->dt = 0.02;
+    opt->taylor_order = 4;
+    opt->hxc_mode = TDKS_HXC_SCF;
+    opt->graph_steps = 16;
+}
+
+const char *tdks_last_error(void) { return g_last_error.c_str(); }
+
+void tdks_destroy(tdks_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->drop_graphs();
+    std::vector<void *> all = c->allocs;
+    for (void *p : all) c->release(p);
+    if (c->h_A) (void)hipHostFree(c->h_A);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->ev_acopy) (void)hipEventDestroy(c->ev_acopy);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_options *opt, tdks_ctx *c) {
+    c->opt = *opt;
+    if (opt->precision != TDKS_FP64 && opt->precision != TDKS_FP32_MIXED)
+        return fail(TDKS_E_ARG, "unknown precision %d", opt->precision);
+    if (opt->taylor_order != 4) return fail(TDKS_E_UNSUPPORTED, "taylor_order must be 4");
+    if (!(opt->dt != 0.0) || !std::isfinite(opt->dt)) return fail(TDKS_E_ARG, "dt must be finite and non-zero");
+    if (opt->hxc_mode < TDKS_HXC_SCF || opt->hxc_mode > TDKS_HXC_NONE)
+        return fail(TDKS_E_ARG, "unknown hxc_mode %d", opt->hxc_mode);
+    c->fp64 = opt->precision == TDKS_FP64;
+    c->n_inst = n_inst;
+    c->chunk = opt->graph_steps == 0 ? 16 : opt->graph_steps;
+    c->caller = static_cast<hipStream_t>(opt->stream);
+    c->inst.resize(n_inst);
+    std::map<std::string, int> table_of;
+    const int kpg = opt->k_per_group > 0 ? opt->k_per_group : 1;
+    for (int i = 0; i < n_inst; ++i) {
+        const tdks_instance_desc &d = desc[i];
+        InstHost &I = c->inst[i];
+        CHK(build_geometry(I, d));
+        if (d.n_atoms < 0 || d.n_atoms > kMaxAtoms) return fail(TDKS_E_UNSUPPORTED, "n_atoms %d outside [0, %d]", d.n_atoms, kMaxAtoms);
+        if (d.n_atoms > 0 && (!d.atom_frac || !d.atom_species || !d.species))
+            return fail(TDKS_E_ARG, "instance %d: atom arrays missing", i);
+        for (int a = 0; a < d.n_atoms; ++a)
+            if (d.atom_species[a] < 0 || d.atom_species[a] >= d.n_species)
+                return fail(TDKS_E_ARG, "instance %d atom %d: species index out of range", i, a);
+        if (d.n_k <= 0 || !d.k_frac) return fail(TDKS_E_ARG, "instance %d: no k-points", i);
+        if (d.n_bands <= 0) return fail(TDKS_E_ARG, "instance %d: no bands", i);
+        I.nk = d.n_k;
+        I.nb = d.n_bands;
+        I.nat = d.n_atoms;
+        I.group = d.group;
+        I.kcart.resize(3 * I.nk);
+        I.kw.resize(I.nk);
+        for (int k = 0; k < I.nk; ++k) {
+            for (int q = 0; q < 3; ++q)
+                I.kcart[3 * k + q] = d.k_frac[3 * k + 0] * I.B[0][q] + d.k_frac[3 * k + 1] * I.B[1][q] +
+                                     d.k_frac[3 * k + 2] * I.B[2][q];
+            I.kw[k] = d.k_weight ? d.k_weight[k] : 1.0 / I.nk;
+        }
+        I.occ.resize(I.nb);
+        for (int b = 0; b < I.nb; ++b) I.occ[b] = d.occ ? d.occ[b] : 2.0;
+        if (opt->hxc_mode == TDKS_HXC_FROZEN) {
+            if (!d.v_hxc_frozen) return fail(TDKS_E_ARG, "instance %d: FROZEN mode needs v_hxc_frozen", i);
+            I.vhxc_frozen.assign(d.v_hxc_frozen, d.v_hxc_frozen + I.ng);
+        }
+        const std::string key = table_key(d);
+        auto it = table_of.find(key);
+        if (it == table_of.end()) {
+            TableSet T;
+            CHK(build_potential_and_tables(I, d, T));
+            c->tables.push_back(std::move(T));
+            I.table = int(c->tables.size()) - 1;
+            table_of[key] = I.table;
+        } else {
+            I.table = it->second;
+            for (int j = 0; j < i; ++j)
+                if (c->inst[j].table == it->second) {
+                    I.vloc = c->inst[j].vloc;
+                    break;
+                }
+        }
+        c->ng_max = std::max(c->ng_max, I.ng);
+    }
+    // shape classes and tiling
+    for (int i = 0; i < n_inst; ++i) {
+        InstHost &I = c->inst[i];
+        int cls = -1;
+        for (size_t s = 0; s < c->classes.size(); ++s) {
+            const ShapeClass &S = c->classes[s];
+            if (S.N[0] == I.N[0] && S.N[1] == I.N[1] && S.N[2] == I.N[2] && S.nonorth == I.nonorth) cls = int(s);
+        }
+        if (cls < 0) {
+            ShapeClass S;
+            for (int q = 0; q < 3; ++q) S.N[q] = I.N[q];
+            S.nonorth = I.nonorth;
+            if (!choose_tiling(S.N, c->fp64, opt->block_size, S.zl, S.block))
+                return fail(TDKS_E_UNSUPPORTED, "no built propagation tiling for grid %dx%dx%d", S.N[0], S.N[1], S.N[2]);
+            c->classes.push_back(S);
+            cls = int(c->classes.size()) - 1;
+        }
+        I.cls = cls;
+        ShapeClass &S = c->classes[cls];
+        const TableSet &T = c->tables[I.table];
+        S.ng_max = std::max(S.ng_max, I.ng);
+        S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
+        S.nat_max = std::max(S.nat_max, T.nat);
+        S.ntask_max = std::max(S.ntask_max, int(T.task.size()));
+    }
+    for (ShapeClass &S : c->classes) {
+        PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
+        const size_t lds = propagate_lds_bytes(c->fp64, a, S.block);
+        if (lds > 160 * 1024)
+            return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of LDS per workgroup", S.N[0], S.N[1],
+                        S.N[2], lds);
+    }
+    // work list: class-major, instance-major, then k groups and band groups
+    for (size_t s = 0; s < c->classes.size(); ++s) {
+        ShapeClass &S = c->classes[s];
+        S.wbeg = int(c->work.size());
+        for (int i = 0; i < n_inst; ++i) {
+            InstHost &I = c->inst[i];
+            if (I.cls != int(s)) continue;
+            const int bpg = (opt->bands_per_group > 0 && opt->bands_per_group < I.nb) ? opt->bands_per_group : I.nb;
+            I.wbeg = int(c->work.size());
+            int slot = 0;
+            for (int k0 = 0; k0 < I.nk; k0 += kpg)
+                for (int b0 = 0; b0 < I.nb; b0 += bpg) {
+                    WorkItem w;
+                    w.inst = i;
+                    w.k0 = k0;
+                    w.nk = std::min(kpg, I.nk - k0);
+                    w.b0 = b0;
+                    w.nb = std::min(bpg, I.nb - b0);
+                    w.slot = slot++;
+                    c->work.push_back(w);
+                }
+            I.wend = int(c->work.size());
+            I.nslot = slot;
+        }
+        S.wend = int(c->work.size());
+    }
+    for (const InstHost &I : c->inst) {
+        if (std::find(c->groups.begin(), c->groups.end(), I.group) == c->groups.end()) c->groups.push_back(I.group);
+    }
+    std::sort(c->groups.begin(), c->groups.end());
+    // device side: stream, events, memory
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_acopy, hipEventDisableTiming));
+    for (TableSet &T : c->tables) {
+        CHK(upload(c, &T.d_ent_pack, T.ent_pack));
+        CHK(upload(c, &T.d_ent_g, T.ent_g));
+        CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
+        CHK(upload(c, &T.d_pt_pack, T.pt_pack));
+        CHK(upload(c, &T.d_pt_g, T.pt_g));
+        CHK(upload(c, &T.d_task, T.task));
+        CHK(upload(c, &T.d_atom_task, T.atom_task));
+        CHK(upload(c, &T.d_atom_tau, T.atom_tau));
+        CHK(upload(c, &T.d_atom_par, T.atom_par));
+    }
+    const size_t ngm = size_t(c->ng_max) * n_inst;
+    std::vector<double> vloc_all(ngm, 0.0), vhxc_all(ngm, 0.0);
+    for (int i = 0; i < n_inst; ++i) {
+        const InstHost &I = c->inst[i];
+        std::copy(I.vloc.begin(), I.vloc.end(), vloc_all.begin() + size_t(i) * c->ng_max);
+        if (!I.vhxc_frozen.empty())
+            std::copy(I.vhxc_frozen.begin(), I.vhxc_frozen.end(), vhxc_all.begin() + size_t(i) * c->ng_max);
+    }
+    CHK(upload(c, &c->d_vloc, vloc_all));
+    CHK(upload(c, &c->d_vhxc, vhxc_all));
+    c->d_rho = static_cast<double *>(c->alloc(sizeof(double) * ngm));
+    c->d_vtot = c->alloc((c->fp64 ? 8 : 4) * ngm);
+    c->d_ctrs = static_cast<int *>(c->alloc(sizeof(int) * 4));
+    c->d_jpre = static_cast<double *>(c->alloc(sizeof(double) * 3 * n_inst));
+    c->d_jobs = static_cast<double *>(c->alloc(sizeof(double) * 3 * n_inst));
+    c->d_Aobs = static_cast<double *>(c->alloc(sizeof(double) * 6));
+    if (!c->d_rho || !c->d_vtot || !c->d_ctrs || !c->d_jpre || !c->d_jobs || !c->d_Aobs)
+        return fail(TDKS_E_OOM, "device allocation failed");
+    HIPCHK(hipMemset(c->d_ctrs, 0, sizeof(int) * 4));
+    HIPCHK(hipMemset(c->d_rho, 0, sizeof(double) * ngm));
+    std::vector<DevInst> dinst(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        InstHost &I = c->inst[i];
+        const TableSet &T = c->tables[I.table];
+        I.d_u = c->alloc(orb_bytes(c, I));
+        if (!I.d_u) return fail(TDKS_E_OOM, "orbital allocation of %zu bytes failed (instance %d)", orb_bytes(c, I), i);
+        CHK(upload(c, &I.d_kcart, I.kcart));
+        CHK(upload(c, &I.d_kw, I.kw));
+        CHK(upload(c, &I.d_occ, I.occ));
+        I.d_rho_part = static_cast<double *>(c->alloc(sizeof(double) * size_t(I.nslot) * I.ng));
+        I.d_j_part = static_cast<double *>(c->alloc(sizeof(double) * 4 * size_t(I.nslot)));
+        if (!I.d_rho_part || !I.d_j_part) return fail(TDKS_E_OOM, "partial-sum allocation failed");
+        DevInst &D = dinst[i];
+        std::memset(&D, 0, sizeof(D));
+        for (int q = 0; q < 3; ++q) D.N[q] = I.N[q];
+        D.ng = I.ng;
+        D.nk = I.nk;
+        D.nb = I.nb;
+        D.nat = T.nat;
+        D.nonorth = I.nonorth;
+        D.ntask = int(T.task.size());
+        D.dV = I.dV;
+        D.omega = I.omega;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                D.lat[a][b] = I.lat[a][b];
+                D.hv[a][b] = I.hv[a][b];
+                D.c[a][b] = I.c[a][b];
+                D.g[a][b] = I.g[a][b];
+            }
+        D.u = I.d_u;
+        D.vtot = static_cast<char *>(c->d_vtot) + size_t(i) * c->ng_max * (c->fp64 ? 8 : 4);
+        D.kcart = I.d_kcart;
+        D.kw = I.d_kw;
+        D.occ = I.d_occ;
+        D.ent_pack = T.d_ent_pack;
+        D.ent_g = T.d_ent_g;
+        D.pt_ptr = T.d_pt_ptr;
+        D.pt_pack = T.d_pt_pack;
+        D.pt_g = T.d_pt_g;
+        D.task = T.d_task;
+        D.atom_task = T.d_atom_task;
+        D.atom_tau = T.d_atom_tau;
+        D.atom_par = T.d_atom_par;
+        D.rho_part = I.d_rho_part;
+        D.j_part = I.d_j_part;
+        D.nslot = I.nslot;
+    }
+    {
+        std::vector<DevInst> tmp = dinst;
+        CHK(upload(c, &c->d_insts, tmp));
+    }
+    CHK(upload(c, &c->d_work, c->work));
+    HIPCHK(launch_vtot(c->d_insts, 0, n_inst, c->ng_max, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64, c->stream));
+    c->jpre.assign(3 * n_inst, 0.0);
+    CHK(ensure_A(c, 64));
+    CHK(ensure_trace(c, 1024));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return TDKS_OK;
+}
+
+int tdks_create(const tdks_instance_desc *inst, int n_inst, const tdks_options *opt, tdks_ctx **out) {
+    if (!out) return fail(TDKS_E_ARG, "out is null");
+    *out = nullptr;
+    if (!inst || n_inst <= 0) return fail(TDKS_E_ARG, "no instances");
+    tdks_options def;
+    tdks_default_options(&def);
+    if (!opt) opt = &def;
+    tdks_ctx *c = new tdks_ctx();
+    int rc = create_impl(inst, n_inst, opt, c);
+    if (rc != TDKS_OK) {
+        std::string msg = g_last_error;
+        tdks_destroy(c);
+        g_last_error = msg;
+        return rc;
+    }
+    *out = c;
+    g_last_error.clear();
+    return TDKS_OK;
+}
+
+int tdks_load_orbitals(tdks_ctx *c, int i, const void *u, int where) {
+    CHK(check_inst(c, i));
+    if (!u) return fail(TDKS_E_ARG, "null orbital pointer");
+    if (where != TDKS_HOST && where != TDKS_DEVICE) return fail(TDKS_E_ARG, "bad where flag");
+    InstHost &I = c->inst[i];
+    CHK(sync_in(c));
+    const size_t n = size_t(I.nk) * I.nb * I.ng;
+    if (c->fp64) {
+        HIPCHK(hipMemcpyAsync(I.d_u, u, 16 * n, where == TDKS_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                              c->stream));
+    } else {
+        const double *src = static_cast<const double *>(u);
+        double *stage = nullptr;
+        if (where == TDKS_HOST) {
+            stage = static_cast<double *>(c->alloc(16 * n));
+            if (!stage) return fail(TDKS_E_OOM, "staging allocation failed");
+            HIPCHK(hipMemcpyAsync(stage, u, 16 * n, hipMemcpyHostToDevice, c->stream));
+            src = stage;
+        }
+        HIPCHK(launch_convert_in(src, I.d_u, n, 0, c->stream));
+        if (stage) {
+            HIPCHK(hipStreamSynchronize(c->stream));
+            c->release(stage);
+        }
+    }
+    // density, v_Hxc and the current before the field (A = 0)
+    const double zero[3] = {0.0, 0.0, 0.0};
+    CHK(observe(c, i, i, zero, c->d_jpre));
+    if (c->opt.hxc_mode == TDKS_HXC_SCF) {
+        HIPCHK(launch_hxc(c->d_insts, i, 1, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64, c->stream));
+    }
+    HIPCHK(hipMemcpyAsync(c->jpre.data() + 3 * i, c->d_jpre + 3 * i, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    I.loaded = true;
+    c->steps_done = 0;
+    CHK(sync_out(c));
+    return TDKS_OK;
+}
+
+int tdks_step(tdks_ctx *c, int n_steps, const double *A_tab) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    if (n_steps < 0) return fail(TDKS_E_ARG, "n_steps < 0");
+    if (n_steps == 0) return TDKS_OK;
+    if (!A_tab) return fail(TDKS_E_ARG, "null A table");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+    CHK(sync_in(c));
+    CHK(ensure_trace(c, size_t(c->steps_done) + n_steps));
+    CHK(ensure_A(c, size_t(n_steps)));
+    HIPCHK(hipEventSynchronize(c->ev_acopy));  // previous copy out of the staging buffer is done
+    std::memcpy(c->h_A, A_tab, sizeof(double) * 6 * n_steps);
+    HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
+    // A row counter restarts for this call; the record counter continues
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    int done = 0;
+    if (c->chunk > 0) {
+        if (!c->g_one) CHK(build_graph(c, 1, &c->g_one));
+        if (c->chunk > 1 && n_steps >= c->chunk && !c->g_chunk) CHK(build_graph(c, c->chunk, &c->g_chunk));
+        while (c->chunk > 1 && n_steps - done >= c->chunk) {
+            HIPCHK(hipGraphLaunch(c->g_chunk, c->stream));
+            done += c->chunk;
+        }
+        while (done < n_steps) {
+            HIPCHK(hipGraphLaunch(c->g_one, c->stream));
+            ++done;
+        }
+    } else {
+        for (; done < n_steps; ++done) CHK(enqueue_step(c));
+    }
+    c->steps_done += n_steps;
+    CHK(sync_out(c));
+    return TDKS_OK;
+}
+
+int tdks_steps_done(tdks_ctx *c) { return c ? c->steps_done : 0; }
+
+int tdks_current(tdks_ctx *c, int mode, double *out, size_t cap, size_t *n_written) {
+    if (!c || !out) return fail(TDKS_E_ARG, "null argument");
+    const size_t ns = size_t(c->steps_done);
+    const size_t rows = (mode == TDKS_PER_GROUP) ? c->groups.size() : size_t(c->n_inst);
+    if (mode != TDKS_PER_GROUP && mode != TDKS_PER_INSTANCE) return fail(TDKS_E_ARG, "bad mode");
+    if (cap < rows * ns * 3) return fail(TDKS_E_ARG, "capacity %zu < %zu", cap, rows * ns * 3);
+    // trace row r of instance i holds J^{r+1}
+    std::vector<double> tr(size_t(c->n_inst) * 3 * std::max<size_t>(ns, 1));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (ns > 0)
+        HIPCHK(hipMemcpy2D(tr.data(), sizeof(double) * 3 * ns, c->d_trace, sizeof(double) * 3 * c->trace_cap,
+                           sizeof(double) * 3 * ns, c->n_inst, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->n_inst; ++i)
+        for (size_t n = 0; n < ns; ++n)
+            for (int q = 0; q < 3; ++q)
+                if (!std::isfinite(tr[(size_t(i) * ns + n) * 3 + q]))
+                    return fail(TDKS_E_NUMERIC, "non-finite current in instance %d at step %zu", i, n + 1);
+    if (mode == TDKS_PER_INSTANCE) {
+        for (int i = 0; i < c->n_inst; ++i)
+            for (size_t n = 0; n < ns; ++n)
+                for (int q = 0; q < 3; ++q)
+                    out[(size_t(i) * ns + n) * 3 + q] = tr[(size_t(i) * ns + n) * 3 + q] - c->jpre[3 * i + q];
+    } else {
+        for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+            int cnt = 0;
+            std::vector<double> acc(3 * ns, 0.0);
+            for (int i = 0; i < c->n_inst; ++i) {
+                if (c->inst[i].group != c->groups[gi]) continue;
+                ++cnt;
+                for (size_t n = 0; n < ns; ++n)
+                    for (int q = 0; q < 3; ++q)
+                        acc[3 * n + q] += tr[(size_t(i) * ns + n) * 3 + q] - c->jpre[3 * i + q];
+            }
+            for (size_t n = 0; n < 3 * ns; ++n) out[gi * 3 * ns + n] = acc[n] / cnt;
+        }
+    }
+    if (n_written) *n_written = rows * ns * 3;
+    return TDKS_OK;
+}
+
+int tdks_current_pre(tdks_ctx *c, double *out) {
+    if (!c || !out) return fail(TDKS_E_ARG, "null argument");
+    std::copy(c->jpre.begin(), c->jpre.end(), out);
+    return TDKS_OK;
+}
+
+int tdks_current_at(tdks_ctx *c, const double *A, double *out) {
+    if (!c || !A || !out) return fail(TDKS_E_ARG, "null argument");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+    CHK(sync_in(c));
+    CHK(observe(c, 0, c->n_inst - 1, A, c->d_jobs));
+    HIPCHK(hipMemcpy(out, c->d_jobs, sizeof(double) * 3 * c->n_inst, hipMemcpyDeviceToHost));
+    CHK(sync_out(c));
+    return TDKS_OK;
+}
+
+int tdks_density(tdks_ctx *c, int i, double *rho_out) {
+    CHK(check_inst(c, i));
+    if (!rho_out) return fail(TDKS_E_ARG, "null output");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(rho_out, c->d_rho + size_t(i) * c->ng_max, sizeof(double) * c->inst[i].ng, hipMemcpyDeviceToHost));
+    return TDKS_OK;
+}
+
+int tdks_vhxc(tdks_ctx *c, int i, double *out) {
+    CHK(check_inst(c, i));
+    if (!out) return fail(TDKS_E_ARG, "null output");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(out, c->d_vhxc + size_t(i) * c->ng_max, sizeof(double) * c->inst[i].ng, hipMemcpyDeviceToHost));
+    return TDKS_OK;
+}
+
+int tdks_vloc(tdks_ctx *c, int i, double *out) {
+    CHK(check_inst(c, i));
+    if (!out) return fail(TDKS_E_ARG, "null output");
+    std::copy(c->inst[i].vloc.begin(), c->inst[i].vloc.end(), out);
+    return TDKS_OK;
+}
+
+int tdks_get_orbitals(tdks_ctx *c, int i, void *u_out, int where) {
+    CHK(check_inst(c, i));
+    if (!u_out) return fail(TDKS_E_ARG, "null output");
+    const InstHost &I = c->inst[i];
+    const size_t n = size_t(I.nk) * I.nb * I.ng;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->fp64) {
+        HIPCHK(hipMemcpy(u_out, I.d_u, 16 * n, where == TDKS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
+        return TDKS_OK;
+    }
+    double *dst = static_cast<double *>(u_out);
+    double *stage = nullptr;
+    if (where == TDKS_HOST) {
+        stage = static_cast<double *>(c->alloc(16 * n));
+        if (!stage) return fail(TDKS_E_OOM, "staging allocation failed");
+        dst = stage;
+    }
+    HIPCHK(launch_convert_out(I.d_u, dst, n, 0, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (stage) {
+        HIPCHK(hipMemcpy(u_out, stage, 16 * n, hipMemcpyDeviceToHost));
+        c->release(stage);
+    }
+    return TDKS_OK;
+}
+
+int tdks_norms(tdks_ctx *c, int i, double *out) {
+    CHK(check_inst(c, i));
+    if (!out) return fail(TDKS_E_ARG, "null output");
+    const InstHost &I = c->inst[i];
+    double *d = static_cast<double *>(c->alloc(sizeof(double) * I.nk * I.nb));
+    if (!d) return fail(TDKS_E_OOM, "allocation failed");
+    HIPCHK(launch_norms(I.d_u, I.nk * I.nb, I.ng, I.dV, c->fp64, d, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(out, d, sizeof(double) * I.nk * I.nb, hipMemcpyDeviceToHost));
+    c->release(d);
+    return TDKS_OK;
+}
+
+int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, int where) {
+    CHK(check_inst(c, i));
+    if (!w || !hw || !A) return fail(TDKS_E_ARG, "null argument");
+    const InstHost &I = c->inst[i];
+    const size_t n = size_t(I.nk) * I.nb * I.ng;
+    const size_t cb = c->fp64 ? 16 : 8;
+    CHK(sync_in(c));
+    double *stage = static_cast<double *>(c->alloc(16 * n));
+    void *win = c->alloc(cb * n);
+    void *wout = c->alloc(cb * n);
+    if (!stage || !win || !wout) return fail(TDKS_E_OOM, "scratch allocation failed");
+    HIPCHK(hipMemcpyAsync(stage, w, 16 * n, where == TDKS_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                          c->stream));
+    HIPCHK(launch_convert_in(stage, win, n, c->fp64, c->stream));
+    double h[6] = {A[0], A[1], A[2], A[0], A[1], A[2]};
+    HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    const ShapeClass &S = c->classes[I.cls];
+    PropArgs a = class_args(c, S, MODE_APPLY, c->d_Aobs, c->d_ctrs + 2);
+    a.work = c->d_work + I.wbeg;
+    a.apply_in = win;
+    a.apply_out = wout;
+    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.nonorth, c->stream));
+    HIPCHK(launch_convert_out(wout, stage, n, c->fp64, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(hw, stage, 16 * n, where == TDKS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
+    c->release(stage);
+    c->release(win);
+    c->release(wout);
+    CHK(sync_out(c));
+    return TDKS_OK;
+}
+
+int tdks_tiling(tdks_ctx *c, int *block, int *zl, int *bands_per_group, int *k_per_group, int *n_groups) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    if (block) *block = c->classes.empty() ? 0 : c->classes[0].block;
+    if (zl) *zl = c->classes.empty() ? 0 : c->classes[0].zl;
+    if (bands_per_group) *bands_per_group = c->work.empty() ? 0 : c->work[0].nb;
+    if (k_per_group) *k_per_group = c->work.empty() ? 0 : c->work[0].nk;
+    if (n_groups) *n_groups = int(c->work.size());
+    return TDKS_OK;
+}
+
+}  // extern "C"
