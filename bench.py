@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the TDKS propagation path on one MI355X.
+
+Headline: batched two-step propagation, 64 independent sub-simulations
+(8^3 coarse Monkhorst-Pack grid x 4^3 uniform shifts, each with its own density
+and Hxc), 8-atom Si-like cell on a 16^3 grid, 16 bands, complex-FP32 propagation
+with FP64 density/current/Hxc, delta kick 1e-3, dt = 0.02.  One step = one
+Taylor-4 step of every orbital of every sub-simulation, plus density, current,
+Poisson + LDA of every sub-simulation.  Metric: k*band*gridpoint*step updates/s.
+
+Also measured: the plain method in FP64 (one instance, direct 8^3 MP grid,
+16^3, 16 bands), the FP32-vs-FP64 deviation of the two-step current over the
+timed steps, the propagation kernel's device time (HIP events on the library
+stream) for the roofline, and the CPU FP64 oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X published FP32 vector peak
+FP64_VECTOR_PEAK_TF = 78.6
+# Algorithmic work per update (one grid point of one orbital advanced one Taylor-4 step):
+BYTES_PER_UPDATE = {"fp32": 16.0, "fp64": 32.0}   # read u once, write u once
+FLOPS_PER_UPDATE = 710.0                          # stencil + potential + projectors + FP64 sums
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tdks_propagate.h", "tdks_internal.h"):
+        with open(os.path.join(ROOT, "paper_2112_00920_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_hash = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def make_two_step(n_inst):
+    import workloads as W
+    wl = W.config("twostep_g16_mp8_s4")
+    return wl, wl.instances[:n_inst]
+
+
+def load_all(prop, insts, seed0, torch):
+    import workloads as W
+    for i, inst in enumerate(insts):
+        u = W.random_orbitals_torch(seed0 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega, device="cuda")
+        prop.load_orbitals(i, u)
+        del u
+    torch.cuda.synchronize()
+
+
+def timed_steps(prop, A, steps, warmup, torch):
+    if warmup:
+        prop.step(A[:warmup])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prop.step(A[warmup:warmup + steps])
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s=15.0):
+    """The oracle as it stands, on one sub-simulation of the two-step workload
+    restricted to its first 2 k-points (16 bands, 16^3), single-threaded."""
+    import workloads as W
+    from oracle import kpoints as okp
+    from oracle import propagate as OP
+    from oracle.hamiltonian import System
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:
+        limiter = None
+    wl = W.config("twostep_g16_mp8_s4")
+    inst = wl.instances[0]
+    kf = okp.kset(inst.kspec)[:2]
+    sysm = System(inst, k_frac=kf)
+    u0 = W.random_orbitals(99, 2, inst.n_bands, inst.grid, inst.omega)
+    run = OP.Run(sysm, u0, wl.dt, "scf")
+    A = wl.field.table(1000, wl.dt)
+    t0 = time.perf_counter()
+    n = 0
+    while n < 2 or time.perf_counter() - t0 < budget_s:
+        run.step(A[n, 0], A[n, 1])
+        n += 1
+    el = time.perf_counter() - t0
+    upd = 2 * inst.n_bands * inst.ng * n
+    return {"value": upd / el, "unit": "k*band*gridpt*step updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one two-step sub-simulation (16^3, 16 bands) restricted to 2 of its 512 k-points, "
+                      f"SCF, {n} steps in {el:.1f} s, NumPy FP64, BLAS limited to 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--instances", type=int, default=64, help="two-step sub-simulations (64 = full workload)")
+    ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the two-step sub-simulations "
+              "are independent and would shard across GPUs without communication, but this build runs on one.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2112_00920_amd as tdks
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    K, Wm = args.steps, args.warmup
+    wl, insts = make_two_step(args.instances)
+    A = wl.field.table(K + Wm + 8, wl.dt)
+    n_inst = len(insts)
+    upd_step = sum(i.n_k * i.n_bands * i.ng for i in insts)
+
+    # ---- headline: batched two-step, FP32 propagation
+    log(f"two-step FP32: {n_inst} sub-simulations x 512 k x 16 bands x 16^3 ({upd_step:.3e} updates/step)")
+    with tdks.Propagator(insts, precision="fp32", dt=wl.dt) as prop:
+        load_all(prop, insts, 1000, torch)
+        til = prop.tiling()
+        el = timed_steps(prop, A, K, Wm, torch)
+        kt = prop.time_kernels(A[K + Wm:K + Wm + 4])
+        dj32 = prop.current(per="instance")
+    value = upd_step * K / el
+    ms_step = 1e3 * el / K
+    log(f"  {value:.3e} updates/s, {ms_step:.2f} ms/step, kernels {kt}, tiling {til}")
+
+    # ---- roofline of the propagation kernel (one launch per step for this workload)
+    upd_launch = upd_step
+    t_launch = kt["propagate_ms"] * 1e-3
+    flops_achieved = FLOPS_PER_UPDATE * upd_launch / t_launch / 1e12
+    bytes_achieved = BYTES_PER_UPDATE["fp32"] * upd_launch / t_launch / 1e9
+    traffic = profiled_traffic("propagate_twostep_g16_fp32_counters.txt")
+    roofline = {"bound": "alu", "achieved": round(flops_achieved, 2), "peak": FP32_VECTOR_PEAK_TF,
+                "unit": "TFLOP/s", "frac": round(flops_achieved / FP32_VECTOR_PEAK_TF, 4),
+                "traffic": traffic,
+                "hbm_algorithmic_GBs": round(bytes_achieved, 1),
+                "hbm_algorithmic_frac": round(bytes_achieved / HBM_PEAK_GBS, 4),
+                "kernel": "k_propagate (Taylor-4 step + density/current partials)",
+                "kernel_ms": round(kt["propagate_ms"], 3), "step_ms_eager": round(kt["step_ms"], 3)}
+
+    # ---- FP32 vs FP64 on the same inputs (first 4 sub-simulations, timed steps)
+    acc = None
+    fp64_twostep = None
+    plain = None
+    if not args.skip_fp64:
+        sub = insts[:4]
+        res = {}
+        for prec in ("fp32", "fp64"):
+            with tdks.Propagator(sub, precision=prec, dt=wl.dt) as p:
+                load_all(p, sub, 1000, torch)
+                p.step(A[:K + Wm])
+                res[prec] = p.current(per="instance").mean(axis=0)
+        ref = res["fp64"]
+        acc = float(np.max(np.abs(res["fp32"] - ref)) / np.max(np.abs(ref)))
+        log(f"  FP32 vs FP64 over {K + Wm} steps (mean of 4 sub-simulations): {acc:.2e} of peak |dJ|")
+        # FP64 batched two-step (same workload, FP64 propagation)
+        with tdks.Propagator(insts, precision="fp64", dt=wl.dt) as p:
+            load_all(p, insts, 1000, torch)
+            el64 = timed_steps(p, A, K, Wm, torch)
+            kt64 = p.time_kernels(A[K + Wm:K + Wm + 2])
+        fp64_twostep = {"value": upd_step * K / el64, "ms_per_step": 1e3 * el64 / K,
+                        "kernel_ms": kt64["propagate_ms"]}
+        log(f"  two-step FP64: {fp64_twostep['value']:.3e} updates/s")
+        # plain method FP64: one instance, direct 8^3 MP grid
+        wl2 = __import__("workloads").config("diamond8_g16_mp8")
+        inst2 = wl2.instances[0]
+        with tdks.Propagator([inst2], precision="fp64", dt=wl2.dt) as p:
+            load_all(p, [inst2], 2000, torch)
+            A2 = wl2.field.table(K + Wm, wl2.dt)
+            el2 = timed_steps(p, A2, K, Wm, torch)
+            kt2 = p.time_kernels(A2[:2])
+        upd2 = inst2.n_k * inst2.n_bands * inst2.ng
+        plain = {"workload": "diamond8_g16_mp8 (plain method, 512 k, 16 bands, 16^3, FP64)",
+                 "value": upd2 * K / el2, "ms_per_step": 1e3 * el2 / K, "kernel_ms": kt2["propagate_ms"],
+                 "hbm_algorithmic_frac": BYTES_PER_UPDATE["fp64"] * upd2 / (kt2["propagate_ms"] * 1e-3) / 1e9
+                 / HBM_PEAK_GBS}
+        log(f"  plain FP64: {plain['value']:.3e} updates/s")
+
+    cpu = None if args.skip_cpu else cpu_baseline()
+    if cpu:
+        log(f"  oracle: {cpu['value']:.3e} updates/s")
+
+    out = {
+        "metric": "k*band*gridpt*step updates/s (batched FP32 two-step)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 reductions)",
+        "data": "synthetic (seeded Gaussian pseudopotential, smooth random orthonormal orbitals)",
+        "config": {"workload": "twostep_g16_mp8_s4", "sub_simulations": n_inst, "coarse_k": "8^3",
+                   "shifts": "4^3 uniform", "bands": 16, "grid": [16, 16, 16], "atoms": 8,
+                   "dt": wl.dt, "field": "kick 1e-3", "hxc": "SCF every step",
+                   "updates_per_step": upd_step, "tiling": til},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_GBs_algorithmic": round(bytes_achieved, 1),
+        "fp64_two_step": fp64_twostep,
+        "fp64_plain": plain,
+        "speedup_fp32_batched_vs_fp64_plain": (value / plain["value"]) if plain else None,
+        "fp32_vs_fp64_dJ_rel_err": acc,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

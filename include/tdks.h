@@ -210,6 +210,14 @@ int tdks_norms(tdks_ctx *ctx, int inst, double *out);
  * kernel's stencil, potential and projector code path. */
 int tdks_apply_h(tdks_ctx *ctx, int inst, const void *w, void *hw, const double *A, int where);
 
+/* Advances every instance by n_steps exactly like tdks_step, but launches the
+ * step's kernels one by one (no graph) with HIP events recorded on the
+ * context's stream around them, and returns the mean device time per step in
+ * out (HOST [3], milliseconds): [0] the propagation kernels (Taylor-4 step with
+ * density and current partials), [1] the reduction, Hxc and counter kernels,
+ * [2] the whole step.  Synchronises.  Same errors as tdks_step. */
+int tdks_time_kernels(tdks_ctx *ctx, int n_steps, const double *A_tab, double *out);
+
 /* Tiling actually used by the first grid shape: threads per workgroup, length of
  * the z-column segment each thread owns, bands and k-points per workgroup, and
  * the number of workgroups per step (all shapes).  Outputs may be NULL. */

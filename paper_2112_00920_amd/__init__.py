@@ -251,6 +251,13 @@ class Propagator:
         _lib.check(self._lib.tdks_apply_h(self._ctx, i, p, ctypes.c_void_p(out.ctypes.data), _ptr(A), _lib.HOST))
         return out
 
+    def time_kernels(self, A_tab) -> dict:
+        """Advance len(A_tab) steps with HIP events around the kernels (ms per step)."""
+        A = np.ascontiguousarray(A_tab, dtype=np.float64).reshape(-1, 2, 3)
+        out = np.zeros(3)
+        _lib.check(self._lib.tdks_time_kernels(self._ctx, len(A), _ptr(A), _ptr(out)))
+        return {"propagate_ms": out[0], "reduce_hxc_ms": out[1], "step_ms": out[2]}
+
     def tiling(self) -> dict:
         v = [ctypes.c_int() for _ in range(5)]
         _lib.check(self._lib.tdks_tiling(self._ctx, *[ctypes.byref(x) for x in v]))

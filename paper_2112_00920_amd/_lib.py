@@ -83,6 +83,7 @@ SYMBOLS = {
     "tdks_apply_h": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                     c_double_p, ctypes.c_int]),
     "tdks_tiling": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_int_p, c_int_p, c_int_p]),
+    "tdks_time_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p]),
 }
 
 _lib = None

@@ -996,6 +996,57 @@ int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, i
     return TDKS_OK;
 }
 
+int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out) {
+    if (!c || !out) return fail(TDKS_E_ARG, "null argument");
+    if (n_steps <= 0) return fail(TDKS_E_ARG, "n_steps must be positive");
+    if (!A_tab) return fail(TDKS_E_ARG, "null A table");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+    CHK(sync_in(c));
+    CHK(ensure_trace(c, size_t(c->steps_done) + n_steps));
+    CHK(ensure_A(c, size_t(n_steps)));
+    HIPCHK(hipEventSynchronize(c->ev_acopy));
+    std::memcpy(c->h_A, A_tab, sizeof(double) * 6 * n_steps);
+    HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    std::vector<hipEvent_t> ev(3 * n_steps);
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    int rc = TDKS_OK;
+    for (int s = 0; s < n_steps && rc == TDKS_OK; ++s) {
+        HIPCHK(hipEventRecord(ev[3 * s], c->stream));
+        for (const ShapeClass &S : c->classes) {
+            PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
+            a.work = c->d_work + S.wbeg;
+            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.nonorth, c->stream));
+        }
+        HIPCHK(hipEventRecord(ev[3 * s + 1], c->stream));
+        HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
+                             c->d_ctrs + 1, c->stream));
+        if (c->opt.hxc_mode == TDKS_HXC_SCF)
+            HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot,
+                              c->fp64, c->stream));
+        HIPCHK(launch_advance(c->d_ctrs, 2, c->stream));
+        HIPCHK(hipEventRecord(ev[3 * s + 2], c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double tp = 0.0, tr = 0.0;
+    for (int s = 0; s < n_steps; ++s) {
+        float a = 0.f, b = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
+        HIPCHK(hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
+        tp += a;
+        tr += b;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    out[0] = tp / n_steps;
+    out[1] = tr / n_steps;
+    out[2] = (tp + tr) / n_steps;
+    c->steps_done += n_steps;
+    CHK(sync_out(c));
+    return rc;
+}
+
 int tdks_tiling(tdks_ctx *c, int *block, int *zl, int *bands_per_group, int *k_per_group, int *n_groups) {
     if (!c) return fail(TDKS_E_ARG, "null context");
     if (block) *block = c->classes.empty() ? 0 : c->classes[0].block;

@@ -95,7 +95,7 @@ STEP_CASES = {
     "d8_8_nograph": ("diamond8", (8, 8, 8), 4, W.KSpec((2, 1, 1)), 5, {"graph_steps": -1}),
     "d8_8_ragged_groups": ("diamond8", (8, 8, 8), 5, W.KSpec((3, 1, 1)), 6,
                            {"bands_per_group": 2, "k_per_group": 2}),
-    "d8_12_c1grid": ("diamond8", (12, 12, 12), 4, W.KSpec((2, 2, 2)), 6, {}),
+    "d8_12": ("diamond8", (12, 12, 12), 4, W.KSpec((2, 2, 2)), 6, {}),
     "fcc2_8": ("fcc2", (8, 8, 8), 3, W.KSpec((2, 2, 2)), 6, {}),
     "s16_8x8x16": ("super16", (8, 8, 16), 6, W.KSpec((1, 1, 2)), 4, {}),
     "d8_16": ("diamond8", (16, 16, 16), 3, W.KSpec((1, 1, 2)), 4, {}),
@@ -219,11 +219,11 @@ def test_free_electron_closed_form_on_gpu(tdks):
             np.testing.assert_allclose(uf[k], t4 ** 3 * u[k], rtol=0, atol=1e-14)
 
 
-def test_c1_configuration_fp64(tdks):
+def test_diamond8_g12_mp2_fp64(tdks):
     """The 8-atom 12^3 cell with 16 bands on the 2^3 MP grid, 20 SCF steps after a kick."""
-    wl = W.config("c1")
+    wl = W.config("diamond8_g12_mp2")
     inst = wl.instances[0]
-    _say("c1 configuration, 20 steps FP64")
+    _say("diamond8 12^3 2^3 MP 16 bands, 20 steps FP64")
     u0 = W.random_orbitals(1, 8, 16, inst.grid, inst.omega)
     A = wl.field.table(20, wl.dt)
     dj, us, rhos, jpre, til = run_gpu(tdks, [inst], [u0], A, "fp64")

@@ -206,25 +206,26 @@ def make_instance(cell: str, grid, n_bands: int, species: List[Species], kspec: 
 
 
 def config(name: str) -> Workload:
-    """Seeded synthetic workloads of the five benchmark configurations.
+    """Seeded synthetic workloads.
 
-    c1: plain method FP64, diamond8 12^3, 16 bands, 2^3 MP, kick, 500 steps.
-    c2: plain method, diamond8 16^3, 16 bands, 8^3 MP (512 k), 4000 steps.
-    c3: two-step, 8^3 coarse x 4^3 uniform shifts = 64 sub-simulations, 16^3.
-    c4: two-step HHG, 4^3 coarse x 4^3 shifts, 20^3, sin^2 pulse.
-    c5: 40 uneven instances (fcc2 / diamond8 16^3 or 20^3 / super16).
+    diamond8_g12_mp2:     plain method, 8-atom cell on 12^3, 16 bands, 2^3 MP, kick, 500 steps.
+    diamond8_g16_mp8:     plain method, 16^3, 16 bands, 8^3 MP (512 k), kick, 4000 steps.
+    twostep_g16_mp8_s4:   two-step, 8^3 coarse x 4^3 uniform shifts = 64 sub-simulations, 16^3.
+    hhg_twostep_g20_mp4_s4: two-step HHG, 4^3 coarse x 4^3 shifts, 20^3, sin^2 pulse.
+    uneven40:             40 uneven instances (fcc2 / diamond8 16^3 or 20^3 / super16).
     """
-    seeds = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}
+    seeds = {"diamond8_g12_mp2": 1, "diamond8_g16_mp8": 2, "twostep_g16_mp8_s4": 3,
+             "hhg_twostep_g20_mp4_s4": 4, "uneven40": 5}
     seed = seeds[name]
     rng = np.random.default_rng(seed)
     sp = draw_species(rng)
-    if name == "c1":
+    if name == "diamond8_g12_mp2":
         inst = [make_instance("diamond8", (12, 12, 12), 16, [sp], KSpec((2, 2, 2)))]
         return Workload(name, inst, 0.02, 500, Field("kick", 1e-3), "scf", seed)
-    if name == "c2":
+    if name == "diamond8_g16_mp8":
         inst = [make_instance("diamond8", (16, 16, 16), 16, [sp], KSpec((8, 8, 8)))]
         return Workload(name, inst, 0.02, 4000, Field("kick", 1e-3), "scf", seed)
-    if name == "c3":
+    if name == "twostep_g16_mp8_s4":
         inst = []
         for j3 in range(4):
             for j2 in range(4):
@@ -232,7 +233,7 @@ def config(name: str) -> Workload:
                     inst.append(make_instance("diamond8", (16, 16, 16), 16, [sp],
                                               KSpec((8, 8, 8), (4, 4, 4), (j1, j2, j3))))
         return Workload(name, inst, 0.02, 4000, Field("kick", 1e-3), "scf", seed)
-    if name == "c4":
+    if name == "hhg_twostep_g20_mp4_s4":
         e_peak = float(rng.uniform(0.01, 0.03))
         omega = 0.0285
         T = 40.0 * 41.341373335  # 40 fs in atomic units of time
@@ -245,7 +246,7 @@ def config(name: str) -> Workload:
         steps = int(round(T / 0.02))
         fld = Field("pulse", direction=(1.0, 0.0, 0.0), A0=e_peak / omega, omega=omega, T=T)
         return Workload(name, inst, 0.02, steps, fld, "scf", seed)
-    if name == "c5":
+    if name == "uneven40":
         inst = []
         for i in range(40):
             kind = int(rng.integers(0, 3))
@@ -308,3 +309,39 @@ def to_dict(obj):
             return [conv(v) for v in x]
         return x
     return conv(asdict(obj))
+
+
+def random_orbitals_torch(seed: int, n_k: int, n_bands: int, grid, omega: float, device="cuda",
+                          mmax: int = 2, k_chunk: int = 64):
+    """Device-side version of random_orbitals for full-size workloads (same
+    recipe, PyTorch's counter-based generator seeded with `seed`): smooth random
+    orbitals [k][b][N3][N2][N1] complex128, orthonormal per k with
+    sum_r conj(u_b) u_b' dV = delta_bb'."""
+    import torch
+
+    N1, N2, N3 = (int(g) for g in grid)
+    ng = N1 * N2 * N3
+    dV = omega / ng
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    ms = torch.arange(-mmax, mmax + 1, device=device, dtype=torch.float64)
+    def waves(n):
+        return torch.exp(2j * torch.pi * torch.outer(ms, torch.arange(n, device=device, dtype=torch.float64)) / n)
+    e1, e2, e3 = waves(N1), waves(N2), waves(N3)
+    nm = len(ms)
+    out = torch.empty((n_k, n_bands, N3, N2, N1), dtype=torch.complex128, device=device)
+    for k0 in range(0, n_k, k_chunk):
+        nk = min(k_chunk, n_k - k0)
+        re = torch.randn((nk, n_bands, nm, nm, nm), generator=gen, device=device, dtype=torch.float64)
+        im = torch.randn((nk, n_bands, nm, nm, nm), generator=gen, device=device, dtype=torch.float64)
+        coef = torch.complex(re, im)
+        # u[k,b,i3,i2,i1] = sum coef[k,b,m3,m2,m1] e3[m3,i3] e2[m2,i2] e1[m1,i1]
+        u = torch.tensordot(coef, e1, dims=([4], [0]))          # k b m3 m2 i1
+        u = torch.tensordot(u, e2, dims=([3], [0]))             # k b m3 i1 i2
+        u = torch.tensordot(u, e3, dims=([2], [0]))             # k b i1 i2 i3
+        u = u.permute(0, 1, 4, 3, 2).reshape(nk, n_bands, ng)   # k b (i3 i2 i1)
+        q, r = torch.linalg.qr(u.transpose(1, 2))               # k ng b
+        d = torch.diagonal(r, dim1=1, dim2=2).real.sign()
+        q = q * d[:, None, :]
+        out[k0:k0 + nk] = (q.transpose(1, 2) / (dV ** 0.5)).reshape(nk, n_bands, N3, N2, N1)
+    return out
