@@ -126,6 +126,8 @@ typedef struct tdks_options {
     int k_per_group;      /* k-points handled by one workgroup (0 = 1)             */
     int block_size;       /* threads per workgroup (0 = automatic)                 */
     int graph_steps;      /* steps captured per HIP graph (0 = 16; <0 disables)    */
+    int waves_per_simd;   /* occupancy target of the propagation kernel: 2 or 4
+                             (0 = automatic); selects the register budget          */
 } tdks_options;
 
 typedef struct tdks_ctx tdks_ctx;
@@ -219,10 +221,11 @@ int tdks_apply_h(tdks_ctx *ctx, int inst, const void *w, void *hw, const double 
 int tdks_time_kernels(tdks_ctx *ctx, int n_steps, const double *A_tab, double *out);
 
 /* Tiling actually used by the first grid shape: threads per workgroup, length of
- * the z-column segment each thread owns, bands and k-points per workgroup, and
- * the number of workgroups per step (all shapes).  Outputs may be NULL. */
-int tdks_tiling(tdks_ctx *ctx, int *block, int *zl, int *bands_per_group, int *k_per_group,
-                int *n_groups);
+ * the z-column segment each thread owns, occupancy target (waves per SIMD), bands
+ * and k-points per workgroup, and the number of workgroups per step (all
+ * shapes).  Outputs may be NULL. */
+int tdks_tiling(tdks_ctx *ctx, int *block, int *zl, int *waves_per_simd, int *bands_per_group,
+                int *k_per_group, int *n_groups);
 
 #ifdef __cplusplus
 }

@@ -73,7 +73,7 @@ class Propagator:
     def __init__(self, instances: Sequence, k_fracs: Optional[Sequence] = None, precision: str = "fp64",
                  dt: float = 0.02, hxc_mode: str = "scf", v_hxc_frozen: Optional[Sequence] = None,
                  bands_per_group: int = 0, k_per_group: int = 0, block_size: int = 0,
-                 graph_steps: int = 16, use_torch: bool = True):
+                 graph_steps: int = 16, waves_per_simd: int = 0, use_torch: bool = True):
         self._lib = _lib.load()
         self._ctx = None
         self.n_inst = len(instances)
@@ -119,6 +119,7 @@ class Propagator:
         opt.k_per_group = int(k_per_group)
         opt.block_size = int(block_size)
         opt.graph_steps = int(graph_steps)
+        opt.waves_per_simd = int(waves_per_simd)
         self._alloc = None
         self._torch = None
         if use_torch:
@@ -259,6 +260,7 @@ class Propagator:
         return {"propagate_ms": out[0], "reduce_hxc_ms": out[1], "step_ms": out[2]}
 
     def tiling(self) -> dict:
-        v = [ctypes.c_int() for _ in range(5)]
+        v = [ctypes.c_int() for _ in range(6)]
         _lib.check(self._lib.tdks_tiling(self._ctx, *[ctypes.byref(x) for x in v]))
-        return dict(zip(["block", "zl", "bands_per_group", "k_per_group", "n_groups"], [x.value for x in v]))
+        return dict(zip(["block", "zl", "waves_per_simd", "bands_per_group", "k_per_group", "n_groups"],
+                        [x.value for x in v]))

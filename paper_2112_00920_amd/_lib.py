@@ -59,6 +59,7 @@ class Options(ctypes.Structure):
         ("k_per_group", ctypes.c_int),
         ("block_size", ctypes.c_int),
         ("graph_steps", ctypes.c_int),
+        ("waves_per_simd", ctypes.c_int),
     ]
 
 
@@ -82,7 +83,7 @@ SYMBOLS = {
     "tdks_norms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p]),
     "tdks_apply_h": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                     c_double_p, ctypes.c_int]),
-    "tdks_tiling": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_int_p, c_int_p, c_int_p]),
+    "tdks_tiling": (ctypes.c_int, [ctypes.c_void_p, c_int_p, c_int_p, c_int_p, c_int_p, c_int_p, c_int_p]),
     "tdks_time_kernels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, c_double_p]),
 }
 

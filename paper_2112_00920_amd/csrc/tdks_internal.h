@@ -29,12 +29,19 @@ struct DevInst {
     const double *kcart;  // [nk][3]
     const double *kw;     // [nk]
     const double *occ;    // [nb]
-    // projectors (k-independent tables, shared between identical cells)
-    const uint32_t *ent_pack;  // atom-major entries: j1+N1 | j2+N2 << 8 | j3+N3 << 16 | atom << 24
-    const double *ent_g;       // radial factor g(d) of each atom-major entry
+    // projectors (k-independent tables, shared between identical cells).  Support
+    // points are grouped by "column image" (atom a, unwrapped in-plane grid offsets
+    // j0, j1): d = j0 a_1/N1 + j1 a_2/N2 + j2 a_3/N3 - tau_a.
+    int ncol;                  // column images
+    const int *col_atom;       // [ncol] atom of each column image
+    const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8
+    const uint32_t *ent_pack;  // atom-major entries: p | (j2 + N3) << 13 | col << 20
+    const float *ent_gf;       // radial factor g(|d|) of each entry, FP32 copy
+    const double *ent_gd;      // ... FP64 copy
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
     const uint32_t *pt_pack;   // point-major copy of ent_pack
-    const double *pt_g;        // point-major copy of ent_g
+    const float *pt_gf;
+    const double *pt_gd;
     const int2 *task;          // [ntask] {first entry, atom | count << 8}
     const int *atom_task;      // [nat+1] first task of each atom
     const double *atom_tau;    // [nat][3] Cartesian positions
@@ -51,11 +58,12 @@ struct WorkItem {
     int inst, k0, nk, b0, nb, slot;
 };
 
-// Built (column-segment length ZL, max threads per workgroup) pairs of the propagation
-// kernel.  N3 must be a multiple of ZL; the block is N1 N2 (N3 / ZL) threads rounded up to 64.
+// Built (column-segment length ZL, max threads per workgroup, min waves per SIMD) triples
+// of the propagation kernel.  N3 must be a multiple of ZL; the block is N1 N2 (N3 / ZL)
+// threads rounded up to 64.
 #define TDKS_PROPAGATE_CONFIGS(X) \
-    X(2, 512) X(3, 512) X(4, 512) X(6, 512) X(8, 512) X(12, 512) X(16, 512) \
-    X(4, 1024) X(8, 1024) X(10, 1024)
+    X(2, 512, 2) X(3, 512, 2) X(4, 512, 2) X(6, 512, 2) X(8, 512, 2) X(12, 512, 2) X(16, 512, 2) \
+    X(4, 512, 4) X(6, 512, 4) X(8, 512, 4) X(4, 1024, 4) X(8, 1024, 4) X(10, 1024, 4)
 
 enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2 };
 
@@ -67,6 +75,7 @@ struct PropArgs {
     double dt;
     int mode;
     int ng_max;            // largest grid of the launch (sizes the LDS orbital buffer)
+    int ncol_max;          // most projector column images of an instance in the launch
     int nmaxd;             // largest N_d of the launch (phase tables)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
@@ -75,10 +84,10 @@ struct PropArgs {
 };
 
 // Host-side launchers implemented in tdks_kernels.hip.
-hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int ppt,
+hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
                             int nonorth, hipStream_t s);
 size_t propagate_lds_bytes(int fp64, const PropArgs &a, int block);
-bool propagate_config_ok(int block, int ppt);
+bool propagate_config_ok(int block, int zl, int minw);
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
                          double *jout, int jstride, const int *rec_ctr, hipStream_t s);
 hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const double *rho,

@@ -7,9 +7,9 @@
 
 namespace tdks {
 
-template <int ZL, int MAXT>
+template <int ZL, int MAXT, int MINW>
 static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
-    auto kern = k_propagate<REAL, ZL, NONORTH_FLAG, MAXT>;
+    auto kern = k_propagate<REAL, ZL, NONORTH_FLAG, MAXT, MINW>;
     const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, a, block);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -18,9 +18,9 @@ static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream
     return hipGetLastError();
 }
 
-hipError_t LAUNCH_NAME(const PropArgs &a, int n_items, int block, int zl, hipStream_t s) {
-#define TDKS_CASE(Z, M) \
-    if (zl == Z && block <= M) return launch_zl<Z, M>(a, n_items, block, s);
+hipError_t LAUNCH_NAME(const PropArgs &a, int n_items, int block, int zl, int minw, hipStream_t s) {
+#define TDKS_CASE(Z, M, O) \
+    if (zl == Z && block <= M && minw == O) return launch_zl<Z, M, O>(a, n_items, block, s);
     TDKS_PROPAGATE_CONFIGS(TDKS_CASE)
 #undef TDKS_CASE
     return hipErrorInvalidValue;

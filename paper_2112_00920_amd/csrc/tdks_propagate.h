@@ -1,21 +1,25 @@
-// Device code of the propagation kernel for CDNA4 (gfx950): real-time TDKS propagation of Bloch orbitals
-// (Sato, arXiv:2112.00920, Sec. II.A Eqs. 1-6) on a real-space grid.
+// Device code of the propagation kernel for CDNA4 (gfx950): real-time TDKS
+// propagation of Bloch orbitals (Sato, arXiv:2112.00920, Sec. II.A, Eqs. 1-6) on
+// a real-space grid.
 //
 // k_propagate: one workgroup owns bands [b0, b0+nb) of k-points [k0, k0+nk) of
-//   one instance.  Each orbital lives in LDS for the whole Taylor-4 step; the
-//   running Taylor sum stays in registers, so HBM sees one read and one write
-//   of every orbital per step.  Per application of h (Eq. 2):
-//     1. projection c_{a,lm} = sum_p f_lm(d) e^{i kappa.d} w(p) dV over the
-//        atom-major support list, split into fixed-length tasks per wave;
-//     2. 4th-order FD kinetic stencil (13 points, 61 for non-orthogonal cells)
-//        read from LDS, + (v_loc + v_Hxc) w, + sum_e e^{-i kappa.d} f E c
-//        (point-major list);
+//   one instance.  Each orbital lives in LDS for the whole Taylor-4 step and the
+//   running Taylor sum stays in registers, so HBM sees one read and one write of
+//   every orbital per step.  Thread t owns the column (i0, i1) of the grid over a
+//   z-segment of ZL points; z neighbours come from registers, in-plane ones from
+//   LDS.  Per application of h (Eq. 2):
+//     1. projections c_{a,lm} = dV sum_p f_lm(d) e^{i kappa.d} w(p) over the
+//        atom-major support list (fixed-length tasks, one wave each);
+//     2. 4th-order FD kinetic stencil (13 points; 61 for non-orthogonal cells)
+//        + (v_loc + v_Hxc) w + sum_a e^{-i kappa.d} sum_lm f_lm E_l c_{a,lm}
+//        (point-major support list);
 //     3. w <- (-i dt / m) h w, acc += w.
-//   After the step the new orbital gives FP64 partials of the density (Eq. 3)
-//   and of the current (Eqs. 5-6) with kappa = k + A(t_{n+1}).
-// k_reduce: deterministic FP64 sum of the per-workgroup partials.
-// k_hxc: one workgroup per instance: Poisson by separable DFT in LDS, Slater
-//   exchange + PZ81 correlation, new v_Hxc and v_loc + v_Hxc.
+//   Projector geometry is stored per "column image" (atom a, unwrapped in-plane
+//   offsets j0, j1): d = dcol + j2 a_3/N3 with dcol = j0 a_1/N1 + j1 a_2/N2 - tau_a,
+//   and e^{i kappa.d} = colphase * e^{i j2 kappa.a_3/N3}; both factors are
+//   rebuilt in LDS once per k-point.  After the step the new orbital yields FP64
+//   partials of the density (Eq. 3) and of the current (Eqs. 5-6) with
+//   kappa = k + A(t_{n+1}).
 #pragma once
 #include "tdks_internal.h"
 
@@ -24,8 +28,8 @@
 namespace tdks {
 
 template <typename R> struct CT;
-template <> struct CT<float> { using T = float2; };
-template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; using Q = float4; };
+template <> struct CT<double> { using T = double2; using Q = double4; };
 
 template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
     T r;
@@ -58,32 +62,45 @@ __device__ __forceinline__ float wave_sum(float v) {
 #define D2C1 (4.0 / 3.0)
 #define D2C2 (-1.0 / 12.0)
 
+// packed projector entry: grid index p | (j2 + N3) << 13 | column image << 20
+__device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &col) {
+    p = int(v & 8191u);
+    j2u = int((v >> 13) & 127u);
+    col = int(v >> 20);
+}
+
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, tab_mid, tab_end, aph_mid, aph_end, part, ec, red, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline PropLds prop_lds(int fp64, int ng_max, int nmaxd, int nat_max,
+__host__ __device__ inline PropLds prop_lds(int fp64, int ng_max, int ncol_max, int nmaxd, int nat_max,
                                             int ntask_max, int block) {
-    size_t c = fp64 ? 16 : 8;
+    const size_t c = fp64 ? 16 : 8;  // complex
+    const size_t r = fp64 ? 8 : 4;   // real
+    const int na = nat_max > 0 ? nat_max : 1;
+    const int nc = ncol_max > 0 ? ncol_max : 1;
     PropLds L;
     size_t o = 0;
     L.W = o; o = al16(o + c * ng_max);
-    L.tab_mid = o; o = al16(o + c * 9 * nmaxd);
-    L.tab_end = o; o = al16(o + 16 * 9 * nmaxd);
-    L.aph_mid = o; o = al16(o + c * nat_max);
-    L.aph_end = o; o = al16(o + 16 * nat_max);
+    L.cold = o; o = al16(o + 4 * r * nc);
+    L.colm = o; o = al16(o + c * nc);
+    L.cole = o; o = al16(o + 16 * nc);
+    L.t2m = o; o = al16(o + c * 3 * nmaxd);
+    L.t2e = o; o = al16(o + 16 * 3 * nmaxd);
+    L.apar = o; o = al16(o + 4 * r * na);
     L.part = o; o = al16(o + c * 4 * (ntask_max > 0 ? ntask_max : 1));
-    L.ec = o; o = al16(o + c * 4 * (nat_max > 0 ? nat_max : 1));
+    L.ec = o; o = al16(o + c * 4 * na);
     L.red = o; o = al16(o + 8 * 8 * (block / 64 + 1));
+    L.jacc = o; o = al16(o + 8 * 4);
     L.total = o;
     return L;
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, const PropArgs &a, int block) {
-    return prop_lds(fp64, a.ng_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
+    return prop_lds(fp64, a.ng_max, a.ncol_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
 }
 
 // Block-wide sum of K <= 8 doubles held by every thread; every thread receives the sums.
@@ -110,14 +127,6 @@ __device__ __forceinline__ void block_sum(double *v, double *red, int nwaves) {
     __syncthreads();
 }
 
-// unwrapped grid offsets j_d (relative to the home cell) of a packed entry
-__device__ __forceinline__ void unpack(uint32_t pk, const int *N, int &j0, int &j1, int &j2, int &a) {
-    j0 = int(pk & 255u) - N[0];
-    j1 = int((pk >> 8) & 255u) - N[1];
-    j2 = int((pk >> 16) & 255u) - N[2];
-    a = int(pk >> 24);
-}
-
 // Opaque copy of a value: stops loop-invariant code motion from hoisting address
 // arithmetic derived from it out of the band / Taylor loops (which would keep one
 // register per neighbour address alive for the whole kernel).
@@ -126,31 +135,20 @@ __device__ __forceinline__ int opq(int x) {
     return x;
 }
 
-__device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
+template <typename R> __device__ __forceinline__ const R *gtab(const DevInst &I);
+template <> __device__ __forceinline__ const float *gtab<float>(const DevInst &I) { return I.ent_gf; }
+template <> __device__ __forceinline__ const double *gtab<double>(const DevInst &I) { return I.ent_gd; }
+template <typename R> __device__ __forceinline__ const R *ptgtab(const DevInst &I);
+template <> __device__ __forceinline__ const float *ptgtab<float>(const DevInst &I) { return I.pt_gf; }
+template <> __device__ __forceinline__ const double *ptgtab<double>(const DevInst &I) { return I.pt_gd; }
 
-// Phase e^{i kappa.d} of a packed projector entry from the separable tables
-// T_d[j_d + N_d] = e^{i j_d kappa.a_d / N_d} and the atom factor e^{-i kappa.tau_a};
-// also returns the wrapped grid index p and the displacement d = sum_d j_d a_d/N_d - tau_a.
-template <typename R, typename C, typename TC>
-__device__ __forceinline__ TC entry_geom(uint32_t pk, const int N0, const int N1, const int N2,
-                                         int ntab, const TC *tab, const TC *aph, const R (&hv)[3][3],
-                                         const double *atom_tau, int &p, int &at, R (&dv)[3]) {
-    const int j0 = int(pk & 255u) - N0;
-    const int j1 = int((pk >> 8) & 255u) - N1;
-    const int j2 = int((pk >> 16) & 255u) - N2;
-    at = int(pk >> 24);
-    p = wrapi(j0, N0) + N0 * (wrapi(j1, N1) + N1 * wrapi(j2, N2));
-    const double *tau = atom_tau + 3 * at;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) dv[q] = R(j0) * hv[0][q] + R(j1) * hv[1][q] + R(j2) * hv[2][q] - R(tau[q]);
-    return cmul(cmul(tab[j0 + N0], tab[ntab + j1 + N1]), cmul(tab[2 * ntab + j2 + N2], aph[at]));
-}
+constexpr int kBatch = 4;  // projector entries a lane loads before using them
 
-// Column ownership: thread t owns grid column (i0, i1) = (t mod N0, (t / N0) mod N1) and the
-// z-segment [seg*ZL, seg*ZL + ZL), seg = t / (N0 N1); BS = N0 N1 (N2 / ZL) threads are active.
-template <typename R, int ZL, bool NONORTH, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
+template <typename R, int ZL, bool NONORTH, int MAXT, int MINW>
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
+void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
+    using Q4 = typename CT<R>::Q;
     extern __shared__ __align__(16) char smem[];
     const WorkItem wi = a.work[blockIdx.x];
     const DevInst &I = a.insts[wi.inst];
@@ -160,18 +158,22 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = BS >> 6;
 
-    const PropLds L = prop_lds(sizeof(R) == 8, a.ng_max, a.nmaxd, a.nat_max, a.ntask_max, BS);
+    const PropLds L = prop_lds(sizeof(R) == 8, a.ng_max, a.ncol_max, a.nmaxd, a.nat_max, a.ntask_max, BS);
     C *W = reinterpret_cast<C *>(smem + L.W);
-    C *tabm = reinterpret_cast<C *>(smem + L.tab_mid);
-    double2 *tabe = reinterpret_cast<double2 *>(smem + L.tab_end);
-    C *aphm = reinterpret_cast<C *>(smem + L.aph_mid);
-    double2 *aphe = reinterpret_cast<double2 *>(smem + L.aph_end);
+    Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
+    C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
+    double2 *cole = reinterpret_cast<double2 *>(smem + L.cole);  // column phase, kappa(t_{n+1})
+    C *t2m = reinterpret_cast<C *>(smem + L.t2m);           // e^{i j2 kappa.a_3/N3}, mid
+    double2 *t2e = reinterpret_cast<double2 *>(smem + L.t2e);
+    Q4 *apar = reinterpret_cast<Q4 *>(smem + L.apar);       // Es dV, Ep dV, Ns, Np per atom
     C *part = reinterpret_cast<C *>(smem + L.part);
     C *EC = reinterpret_cast<C *>(smem + L.ec);
     double *red = reinterpret_cast<double *>(smem + L.red);
+    double *jsum = reinterpret_cast<double *>(smem + L.jacc);  // current partial of this workgroup
 
-    const int ntab = 3 * a.nmaxd;  // per-dimension stride in the phase tables
     const R *vtot = reinterpret_cast<const R *>(I.vtot);
+    const R *gt = gtab<R>(I);
+    const R *pgt = ptgtab<R>(I);
     const int plane = N0 * N1;
     const int nseg = N2 / ZL;
     const bool active = tid < plane * nseg;
@@ -190,19 +192,35 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
     oy[3] = ((i1 >= 2) ? -2 : N1 - 2) * N0;
 
     const double *Am = a.A_tab + 6 * (*a.step_ctr);
-    double jacc[3] = {0.0, 0.0, 0.0};
+    if (tid < 3) jsum[tid] = 0.0;
     const double dV = I.dV;
     const int nat = I.nat;
     const int ntask = I.ntask;
-    R hvr[3][3];
-    double hvd[3][3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            hvd[d][q] = I.hv[d][q];
-            hvr[d][q] = R(I.hv[d][q]);
-        }
+    const int ncol = I.ncol;
+    const R h2x = R(I.hv[2][0]), h2y = R(I.hv[2][1]), h2z = R(I.hv[2][2]);
+
+    // k-independent projector geometry of this instance into LDS
+    for (int c = tid; c < ncol; c += BS) {
+        const int at = I.col_atom[c];
+        const int j01 = I.col_j01[c];
+        const double j0 = double((j01 & 255) - N0), j1 = double((j01 >> 8) - N1);
+        const double *tau = I.atom_tau + 3 * at;
+        Q4 q;
+        q.x = R(j0 * I.hv[0][0] + j1 * I.hv[1][0] - tau[0]);
+        q.y = R(j0 * I.hv[0][1] + j1 * I.hv[1][1] - tau[1]);
+        q.z = R(j0 * I.hv[0][2] + j1 * I.hv[1][2] - tau[2]);
+        q.w = R(at);
+        cold[c] = q;
+    }
+    for (int at = tid; at < nat; at += BS) {
+        const double *par = I.atom_par + 4 * at;
+        Q4 q;
+        q.x = R(par[0] * dV);
+        q.y = R(par[1] * dV);
+        q.z = R(par[2]);
+        q.w = R(par[3]);
+        apar[at] = q;
+    }
 
     R vz[ZL];
     double rho[ZL];
@@ -229,56 +247,62 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
 #pragma unroll 1
     for (int kk = 0; kk < wi.nk; ++kk) {
         const int k = wi.k0 + kk;
+        // kappa-dependent coefficients: -i kappa.grad_FD and |kappa|^2 / 2, kappa = k + A(t_n + dt/2)
+        R b1[3], b2[3];
+        R c0;
+        {
+            double km[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) km[d] = I.kcart[3 * k + d] + Am[d];
+            const double kk2 = km[0] * km[0] + km[1] * km[1] + km[2] * km[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double kc = km[0] * I.c[d][0] + km[1] * I.c[d][1] + km[2] * I.c[d][2];
+                b1[d] = R(kc * D1C1);
+                b2[d] = R(kc * D1C2);
+            }
+            c0 = R(c0l + 0.5 * kk2);
+        }
+
+        // phases: column images and the a_3 factor, for kappa(t_n + dt/2) and kappa(t_{n+1})
+        __syncthreads();
+        const double inv_pi = 0.3183098861837907;
         double km[3], ke[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             km[d] = I.kcart[3 * k + d] + Am[d];
             ke[d] = I.kcart[3 * k + d] + Am[3 + d];
         }
-        const double wk = I.kw[k];
-        // kappa-dependent coefficients: -i kappa.grad_FD and |kappa|^2 / 2
-        R b1[3], b2[3];
-        const double kk2 = km[0] * km[0] + km[1] * km[1] + km[2] * km[2];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double kc = km[0] * I.c[d][0] + km[1] * I.c[d][1] + km[2] * I.c[d][2];
-            b1[d] = R(kc * D1C1);
-            b2[d] = R(kc * D1C2);
+        for (int c = tid; c < ncol; c += BS) {
+            const int at = I.col_atom[c];
+            const int j01 = I.col_j01[c];
+            const double j0 = double((j01 & 255) - N0), j1 = double((j01 >> 8) - N1);
+            const double *tau = I.atom_tau + 3 * at;
+            double dcx = j0 * I.hv[0][0] + j1 * I.hv[1][0] - tau[0];
+            double dcy = j0 * I.hv[0][1] + j1 * I.hv[1][1] - tau[1];
+            double dcz = j0 * I.hv[0][2] + j1 * I.hv[1][2] - tau[2];
+            double sm, cm, se, ce;
+            sincospi((km[0] * dcx + km[1] * dcy + km[2] * dcz) * inv_pi, &sm, &cm);
+            sincospi((ke[0] * dcx + ke[1] * dcy + ke[2] * dcz) * inv_pi, &se, &ce);
+            C t;
+            t.x = R(cm);
+            t.y = R(sm);
+            colm[c] = t;
+            cole[c] = make_double2(ce, se);
         }
-        const R c0 = R(c0l + 0.5 * kk2);
-
-        // phase tables for kappa(t_n + dt/2) (propagation precision) and kappa(t_{n+1}) (FP64)
-        __syncthreads();
-        for (int idx = tid; idx < 3 * ntab; idx += BS) {
-            const int d = idx / ntab, jj = idx - d * ntab;
-            const int n = I.N[d];
-            if (jj < 3 * n) {
-                const double j = double(jj - n);
-                const double inv_pi_n = 0.3183098861837907 / n;
-                const double thm = (km[0] * I.lat[d][0] + km[1] * I.lat[d][1] + km[2] * I.lat[d][2]) * inv_pi_n;
-                const double the = (ke[0] * I.lat[d][0] + ke[1] * I.lat[d][1] + ke[2] * I.lat[d][2]) * inv_pi_n;
+        {
+            const double thm = (km[0] * I.hv[2][0] + km[1] * I.hv[2][1] + km[2] * I.hv[2][2]) * inv_pi;
+            const double the = (ke[0] * I.hv[2][0] + ke[1] * I.hv[2][1] + ke[2] * I.hv[2][2]) * inv_pi;
+            for (int j = tid; j < 3 * N2; j += BS) {
                 double sm, cm, se, ce;
-                sincospi(j * thm, &sm, &cm);
-                sincospi(j * the, &se, &ce);
+                sincospi(double(j - N2) * thm, &sm, &cm);
+                sincospi(double(j - N2) * the, &se, &ce);
                 C t;
                 t.x = R(cm);
                 t.y = R(sm);
-                tabm[idx] = t;
-                tabe[idx] = make_double2(ce, se);
+                t2m[j] = t;
+                t2e[j] = make_double2(ce, se);
             }
-        }
-        for (int at = tid; at < nat; at += BS) {
-            const double *tau = I.atom_tau + 3 * at;
-            const double pm = (km[0] * tau[0] + km[1] * tau[1] + km[2] * tau[2]) * 0.3183098861837907;
-            const double pe = (ke[0] * tau[0] + ke[1] * tau[1] + ke[2] * tau[2]) * 0.3183098861837907;
-            double sm, cm, se, ce;
-            sincospi(pm, &sm, &cm);
-            sincospi(pe, &se, &ce);
-            C t;
-            t.x = R(cm);
-            t.y = R(-sm);
-            aphm[at] = t;
-            aphe[at] = make_double2(ce, -se);
         }
 
 #pragma unroll 1
@@ -288,7 +312,7 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
             C *ug = reinterpret_cast<C *>(I.u) + orb;
             const C *src = (a.mode == MODE_APPLY) ? reinterpret_cast<const C *>(a.apply_in) + orb : ug;
             C acc[ZL], wc[ZL];
-            __syncthreads();  // previous users of W are done
+            __syncthreads();  // previous users of W (and the phase tables) are done
             const int pl = opq(pbase + plane * z0);
 #pragma unroll
             for (int z = 0; z < ZL; ++z) {
@@ -310,26 +334,38 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                 // ---- 1. projections c = <P|w> (atom-major tasks, one wave each)
                 for (int t = wave; t < ntask; t += NW) {
                     const int2 tk = I.task[t];
-                    const int e0 = tk.x, cnt = tk.y >> 8;
+                    const int e0 = tk.x, cnt = tk.y >> 8, at = tk.y & 255;
+                    const Q4 ap = apar[at];
                     C s[4];
 #pragma unroll
                     for (int l = 0; l < 4; ++l) { s[l].x = R(0); s[l].y = R(0); }
-                    for (int e = e0 + lane; e < e0 + cnt; e += 64) {
-                        int p, at;
-                        R dv[3];
-                        const C ph = entry_geom<R, C, C>(I.ent_pack[e], N0, N1, N2, ntab, tabm, aphm,
-                                                         hvr, I.atom_tau, p, at, dv);
-                        const C x = cmul(ph, W[p]);
-                        const R gv = R(I.ent_g[e]);
-                        const double *par = I.atom_par + 4 * at;
-                        const R fs = R(par[2]) * gv, fp = R(par[3]) * gv;
-                        s[0].x += fs * x.x;
-                        s[0].y += fs * x.y;
+                    for (int base = lane; base < cnt; base += 64 * kBatch) {
+                        uint32_t pk[kBatch];
+                        R gv[kBatch];
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const R f = fp * dv[q];
-                            s[1 + q].x += f * x.x;
-                            s[1 + q].y += f * x.y;
+                        for (int q = 0; q < kBatch; ++q) {
+                            const int i = base + 64 * q;
+                            pk[q] = (i < cnt) ? I.ent_pack[e0 + i] : 0u;
+                            gv[q] = (i < cnt) ? gt[e0 + i] : R(0);
+                        }
+#pragma unroll
+                        for (int q = 0; q < kBatch; ++q) {
+                            int p, j2u, col;
+                            ent_unpack(pk[q], p, j2u, col);
+                            const Q4 cd = cold[col];
+                            const C ph = cmul(colm[col], t2m[j2u]);
+                            const C x = cmul(ph, W[p]);
+                            const R j2 = R(j2u - N2);
+                            const R fs = ap.z * gv[q], fp = ap.w * gv[q];
+                            const R dx = cd.x + j2 * h2x, dy = cd.y + j2 * h2y, dz = cd.z + j2 * h2z;
+                            s[0].x += fs * x.x;
+                            s[0].y += fs * x.y;
+                            s[1].x += fp * dx * x.x;
+                            s[1].y += fp * dx * x.y;
+                            s[2].x += fp * dy * x.x;
+                            s[2].y += fp * dy * x.y;
+                            s[3].x += fp * dz * x.x;
+                            s[3].y += fp * dz * x.y;
                         }
                     }
 #pragma unroll
@@ -353,7 +389,7 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                         s.x += v.x;
                         s.y += v.y;
                     }
-                    const R e = R(I.atom_par[4 * at + (l == 0 ? 0 : 1)] * dV);
+                    const R e = (l == 0) ? apar[at].x : apar[at].y;  // E_l dV
                     s.x *= e;
                     s.y *= e;
                     EC[idx] = s;
@@ -362,15 +398,13 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                 // ---- 2. h w along the owned column segment
                 // (opaque copies keep the compiler from hoisting every neighbour address
                 // out of the band and Taylor loops, which would pin them in registers)
-                int pb = pbase;
+                const int pb = opq(pbase);
                 int oxl[4], oyl[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    oxl[s] = ox[s];
-                    oyl[s] = oy[s];
+                    oxl[s] = opq(ox[s]);
+                    oyl[s] = opq(oy[s]);
                 }
-                asm volatile("" : "+v"(pb), "+v"(oxl[0]), "+v"(oxl[1]), "+v"(oxl[2]), "+v"(oxl[3]));
-                asm volatile("" : "+v"(oyl[0]), "+v"(oyl[1]), "+v"(oyl[2]), "+v"(oyl[3]));
                 C hz[ZL];
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
@@ -452,26 +486,23 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                             h.y += cx[q] * tot.y;
                         }
                     }
-                    // non-local: sum over the projector entries touching p
+                    // non-local part: projector entries touching p
                     const int e1 = I.pt_ptr[p + 1];
                     for (int e = I.pt_ptr[p]; e < e1; ++e) {
-                        int pp, at;
-                        R dv[3];
-                        const C ph = entry_geom<R, C, C>(I.pt_pack[e], N0, N1, N2, ntab, tabm, aphm,
-                                                         hvr, I.atom_tau, pp, at, dv);
-                        const R gv = R(I.pt_g[e]);
-                        const double *par = I.atom_par + 4 * at;
-                        const R fs = R(par[2]) * gv, fp = R(par[3]) * gv;
+                        int pp, j2u, col;
+                        ent_unpack(I.pt_pack[e], pp, j2u, col);
+                        const R gv = pgt[e];
+                        const Q4 cd = cold[col];
+                        const int at = int(cd.w);
+                        const Q4 ap = apar[at];
+                        const C ph = cmul(colm[col], t2m[j2u]);
+                        const R j2 = R(j2u - N2);
+                        const R fs = ap.z * gv, fp = ap.w * gv;
+                        const R dx = cd.x + j2 * h2x, dy = cd.y + j2 * h2y, dz = cd.z + j2 * h2z;
                         const C *ec = EC + 4 * at;
                         C sum;
-                        sum.x = fs * ec[0].x;
-                        sum.y = fs * ec[0].y;
-#pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            const R f = fp * dv[q];
-                            sum.x += f * ec[1 + q].x;
-                            sum.y += f * ec[1 + q].y;
-                        }
+                        sum.x = fs * ec[0].x + fp * (dx * ec[1].x + dy * ec[2].x + dz * ec[3].x);
+                        sum.y = fs * ec[0].y + fp * (dx * ec[1].y + dy * ec[2].y + dz * ec[3].y);
                         const C v = cmulc(ph, sum);  // e^{-i kappa.d} * sum
                         h.x += v.x;
                         h.y += v.y;
@@ -514,7 +545,7 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                 }
             }
             __syncthreads();
-            const double fo = wk * I.occ[b];
+            const double fo = I.kw[k] * I.occ[b];
             double qn[4] = {0.0, 0.0, 0.0, 0.0};  // Q_d = sum Im(conj(u) D1_d u), and sum |u|^2
             const int pk0 = opq(pbase);
             int oxk[4], oyk[4];
@@ -528,7 +559,8 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                 for (int z = 0; z < ZL; ++z) {
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
-                    const double ux = double(acc[z].x), uy = double(acc[z].y);
+                    const C u = W[p];
+                    const double ux = double(u.x), uy = double(u.y);
                     const double n2 = ux * ux + uy * uy;
                     rho[z] += fo * n2;
                     qn[3] += n2;
@@ -550,13 +582,16 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                         }
                         const C p1 = W[p + o[0]], m1 = W[p + o[1]];
                         const C p2 = W[p + o[2]], m2 = W[p + o[3]];
-                        const double dx = D1C1 * (double(p1.x) - double(m1.x)) + D1C2 * (double(p2.x) - double(m2.x));
-                        const double dy = D1C1 * (double(p1.y) - double(m1.y)) + D1C2 * (double(p2.y) - double(m2.y));
-                        qn[d] += ux * dy - uy * dx;
+                        // D1 in the orbital precision, the products accumulated in FP64
+                        const R dx = R(D1C1) * (p1.x - m1.x) + R(D1C2) * (p2.x - m2.x);
+                        const R dy = R(D1C1) * (p1.y - m1.y) + R(D1C2) * (p2.y - m2.y);
+                        qn[d] += ux * double(dy) - uy * double(dx);
                     }
                 }
             }
-            // non-local current 2 E_l Im(conj(c_d) c): one wave per atom, one channel at a time
+            // non-local current: one wave per atom.  With c = <P|u>, c_d = <d P|u> the
+            // commutator term is sum_lm 2 E_l Im(conj(c_d,lm) c_lm); since
+            // d_j f_s = (N_s/N_p) f_p,j, only c_s, c_p,i and Q_ij = <d_j P_p,i|u> are needed.
             double jnl[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
             for (int at = wave; at < nat; at += NW) {
@@ -564,38 +599,66 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
                 const int tl = I.atom_task[at + 1] - 1;
                 const int e_end = I.task[tl].x + (I.task[tl].y >> 8);
                 const double *par = I.atom_par + 4 * at;
-#pragma unroll 1
-                for (int l = 0; l < 4; ++l) {
-                    double2 cs = make_double2(0.0, 0.0);
-                    double2 cd[3];
+                const double ns = par[2], np = par[3];
+                double2 cs = make_double2(0.0, 0.0), cp[3], qq[6];
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) cd[q] = make_double2(0.0, 0.0);
-                    for (int e = e_beg + lane; e < e_end; e += 64) {
-                        int p, at2;
-                        double dv[3];
-                        const double2 ph = entry_geom<double, double2, double2>(
-                            I.ent_pack[e], N0, N1, N2, ntab, tabe, aphe, hvd, I.atom_tau, p, at2, dv);
-                        const C wv = W[p];
-                        const double2 x = cmul(ph, make_double2(double(wv.x), double(wv.y)));
-                        const double gv = I.ent_g[e];
-                        const double f = (l == 0) ? par[2] * gv : par[3] * gv * dv[l - 1];
-                        cs.x += f * x.x;
-                        cs.y += f * x.y;
+                for (int i = 0; i < 3; ++i) cp[i] = make_double2(0.0, 0.0);
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) {
-                            cd[q].x += dv[q] * f * x.x;
-                            cd[q].y += dv[q] * f * x.y;
-                        }
+                for (int i = 0; i < 6; ++i) qq[i] = make_double2(0.0, 0.0);
+                for (int e = e_beg + lane; e < e_end; e += 64) {
+                    int p, j2u, col;
+                    ent_unpack(I.ent_pack[e], p, j2u, col);
+                    const double gv = double(gt[e]);
+                    const Q4 cd = cold[col];
+                    const double2 ph = cmul(cole[col], t2e[j2u]);
+                    const C wv = W[p];
+                    const double2 x = cmul(ph, make_double2(double(wv.x), double(wv.y)));
+                    const double j2 = double(j2u - N2);
+                    const double d[3] = {double(cd.x) + j2 * I.hv[2][0], double(cd.y) + j2 * I.hv[2][1],
+                                         double(cd.z) + j2 * I.hv[2][2]};
+                    const double fs = ns * gv, fp = np * gv;
+                    cs.x += fs * x.x;
+                    cs.y += fs * x.y;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const double f = fp * d[i];
+                        cp[i].x += f * x.x;
+                        cp[i].y += f * x.y;
                     }
-                    cs.x = wave_sum(cs.x);
-                    cs.y = wave_sum(cs.y);
-                    const double El = par[l == 0 ? 0 : 1];
+                    // Q_ij, i <= j: 00 11 22 01 02 12
+                    const double q00 = fp * d[0] * d[0], q11 = fp * d[1] * d[1], q22 = fp * d[2] * d[2];
+                    const double q01 = fp * d[0] * d[1], q02 = fp * d[0] * d[2], q12 = fp * d[1] * d[2];
+                    qq[0].x += q00 * x.x; qq[0].y += q00 * x.y;
+                    qq[1].x += q11 * x.x; qq[1].y += q11 * x.y;
+                    qq[2].x += q22 * x.x; qq[2].y += q22 * x.y;
+                    qq[3].x += q01 * x.x; qq[3].y += q01 * x.y;
+                    qq[4].x += q02 * x.x; qq[4].y += q02 * x.y;
+                    qq[5].x += q12 * x.x; qq[5].y += q12 * x.y;
+                }
+                cs.x = wave_sum(cs.x);
+                cs.y = wave_sum(cs.y);
 #pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        cd[q].x = wave_sum(cd[q].x);
-                        cd[q].y = wave_sum(cd[q].y);
-                        jnl[q] += 2.0 * El * dV * dV * (cd[q].x * cs.y - cd[q].y * cs.x);
+                for (int i = 0; i < 3; ++i) {
+                    cp[i].x = wave_sum(cp[i].x);
+                    cp[i].y = wave_sum(cp[i].y);
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) {
+                    qq[i].x = wave_sum(qq[i].x);
+                    qq[i].y = wave_sum(qq[i].y);
+                }
+                const double Es = par[0], Ep = par[1];
+                const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    // s channel: c_{d_j,s} = (N_s/N_p) c_{p,j}
+                    double v = Es * (ns / np) * (cp[j].x * cs.y - cp[j].y * cs.x);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const double2 qv = qq[qi[i][j]];
+                        v += Ep * (qv.x * cp[i].y - qv.y * cp[i].x);
                     }
+                    jnl[j] += 2.0 * dV * dV * v;
                 }
             }
             if (lane != 0) {
@@ -608,7 +671,8 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     const double kin = dV * (I.c[0][q] * v7[0] + I.c[1][q] * v7[1] + I.c[2][q] * v7[2]);
-                    jacc[q] += fo * (kin + ke[q] * nrm + v7[4 + q]);
+                    const double keq = I.kcart[3 * k + q] + Am[3 + q];
+                    jsum[q] += fo * (kin + keq * nrm + v7[4 + q]);
                 }
             }
         }
@@ -620,11 +684,12 @@ __global__ __launch_bounds__(MAXT) void k_propagate(PropArgs a) {
 #pragma unroll
         for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = rho[z];
     }
+    __syncthreads();
     if (tid == 0) {
         double *jp = I.j_part + 4 * wi.slot;
-        jp[0] = jacc[0];
-        jp[1] = jacc[1];
-        jp[2] = jacc[2];
+        jp[0] = jsum[0];
+        jp[1] = jsum[1];
+        jp[2] = jsum[2];
         jp[3] = 0.0;
     }
 }

@@ -45,15 +45,20 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 struct TableSet {
+    std::vector<int> col_atom, col_j01;
     std::vector<uint32_t> ent_pack, pt_pack;
     std::vector<double> ent_g, pt_g;
-    std::vector<int> pt_ptr, atom_task;
+    std::vector<float> ent_gf, pt_gf;
+    std::vector<int> pt_ptr, atom_task, atom_ent;  // atom_ent: [nat+1] first entry of each atom
     std::vector<int2> task;
     std::vector<double> atom_tau, atom_par;
     int nat = 0;
+    int cls = -1;
     // device copies
+    int *d_col_atom = nullptr, *d_col_j01 = nullptr;
     uint32_t *d_ent_pack = nullptr, *d_pt_pack = nullptr;
     double *d_ent_g = nullptr, *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
+    float *d_ent_gf = nullptr, *d_pt_gf = nullptr;
     int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
     int2 *d_task = nullptr;
 };
@@ -80,9 +85,9 @@ struct InstHost {
 struct ShapeClass {
     int N[3];
     bool nonorth;
-    int zl = 0, block = 0;
+    int zl = 0, block = 0, minw = 0;
     int wbeg = 0, wend = 0;
-    int ng_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
+    int ng_max = 0, ncol_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
 };
 
 }  // namespace
@@ -245,14 +250,20 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                     }
                 }
     }
-    // projector support: points within Rc of exactly one image of each atom
-    struct Ent { int p; uint32_t pack; double g; };
-    std::vector<std::vector<Ent>> per_atom(nat);
+    // projector support: points within Rc of exactly one image of each atom, grouped by
+    // column image (atom, unwrapped j0, j1) and ordered by (column image, j2)
+    struct Ent { int col; int j2u; int p; double g; };
+    std::vector<Ent> ents;
+    T.col_atom.clear();
+    T.col_j01.clear();
+    T.atom_ent.assign(nat + 1, 0);
     for (int a = 0; a < nat; ++a) {
+        T.atom_ent[a] = int(ents.size());
         const tdks_species &sp = d.species[d.atom_species[a]];
         if (!(sp.Rc > 0.0) || !(sp.rc > 0.0)) return fail(TDKS_E_ARG, "species radii must be positive");
         const double gcut = std::exp(-sp.Rc * sp.Rc / (2.0 * sp.rc * sp.rc));
         std::vector<int> hits(I.ng, 0);
+        std::map<int, std::vector<std::pair<int, std::pair<int, double>>>> bycol;  // j01 -> (j2u, (p, g))
         for (int n0 = -2; n0 <= 2; ++n0)
             for (int n1 = -2; n1 <= 2; ++n1)
                 for (int n2 = -2; n2 <= 2; ++n2) {
@@ -267,39 +278,35 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                             return fail(TDKS_E_ARG, "atom %d: projector radius %.3f reaches two images of the "
                                         "same atom (must be below half the shortest lattice translation)", a, sp.Rc);
                         const int i0 = p % I.N[0], i1 = (p / I.N[0]) % I.N[1], i2 = p / (I.N[0] * I.N[1]);
-                        const int j0 = i0 - n0 * I.N[0], j1 = i1 - n1 * I.N[1], j2 = i2 - n2 * I.N[2];
-                        const int u0 = j0 + I.N[0], u1 = j1 + I.N[1], u2 = j2 + I.N[2];
+                        const int u0 = i0 - n0 * I.N[0] + I.N[0], u1 = i1 - n1 * I.N[1] + I.N[1];
+                        const int u2 = i2 - n2 * I.N[2] + I.N[2];
                         if (u0 < 0 || u0 >= 3 * I.N[0] || u1 < 0 || u1 >= 3 * I.N[1] || u2 < 0 || u2 >= 3 * I.N[2])
                             return fail(TDKS_E_ARG, "atom %d: projector support outside the neighbouring cells", a);
                         const double g = std::max(0.0, std::exp(-d2 / (2.0 * sp.rc * sp.rc)) - gcut);
-                        const uint32_t pack = uint32_t(u0) | (uint32_t(u1) << 8) | (uint32_t(u2) << 16) |
-                                              (uint32_t(a) << 24);
-                        per_atom[a].push_back({p, pack, g});
+                        bycol[u0 | (u1 << 8)].push_back({u2, {p, g}});
                     }
                 }
-        std::sort(per_atom[a].begin(), per_atom[a].end(), [](const Ent &x, const Ent &y) { return x.p < y.p; });
+        if (bycol.empty()) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
+        for (auto &kv : bycol) {
+            const int col = int(T.col_atom.size());
+            T.col_atom.push_back(a);
+            T.col_j01.push_back(kv.first);
+            std::sort(kv.second.begin(), kv.second.end());
+            for (auto &e : kv.second) ents.push_back({col, e.first, e.second.first, e.second.second});
+        }
     }
+    T.atom_ent[nat] = int(ents.size());
+    if (T.col_atom.size() >= 4096)
+        return fail(TDKS_E_UNSUPPORTED, "%zu projector column images exceed 4095", T.col_atom.size());
+    std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
     T.ent_pack.clear();
     T.ent_g.clear();
-    T.task.clear();
-    T.atom_task.assign(nat + 1, 0);
-    std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
-    for (int a = 0; a < nat; ++a) {
-        T.atom_task[a] = int(T.task.size());
-        const int base = int(T.ent_pack.size());
-        const int cnt = int(per_atom[a].size());
-        if (cnt == 0) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
-        for (const Ent &e : per_atom[a]) {
-            T.ent_pack.push_back(e.pack);
-            T.ent_g.push_back(e.g);
-            per_point[e.p].push_back({e.pack, e.g});
-        }
-        for (int s = 0; s < cnt; s += kTaskLen) {
-            const int len = std::min(kTaskLen, cnt - s);
-            T.task.push_back(make_int2(base + s, a | (len << 8)));
-        }
+    for (const Ent &e : ents) {
+        const uint32_t pack = uint32_t(e.p) | (uint32_t(e.j2u) << 13) | (uint32_t(e.col) << 20);
+        T.ent_pack.push_back(pack);
+        T.ent_g.push_back(e.g);
+        per_point[e.p].push_back({pack, e.g});
     }
-    T.atom_task[nat] = int(T.task.size());
     T.pt_ptr.assign(I.ng + 1, 0);
     T.pt_pack.clear();
     T.pt_g.clear();
@@ -311,7 +318,25 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         }
     }
     T.pt_ptr[I.ng] = int(T.pt_pack.size());
+    T.ent_gf.assign(T.ent_g.begin(), T.ent_g.end());
+    T.pt_gf.assign(T.pt_g.begin(), T.pt_g.end());
     return TDKS_OK;
+}
+
+// projection tasks: contiguous entry ranges of one atom, about two per wave of the block
+void build_tasks(TableSet &T, int block) {
+    const int nwaves = std::max(1, block / 64);
+    const int total = T.atom_ent[T.nat];
+    int len = (total + 2 * nwaves - 1) / (2 * nwaves);
+    len = std::max(64, (len + 63) / 64 * 64);
+    T.task.clear();
+    T.atom_task.assign(T.nat + 1, 0);
+    for (int a = 0; a < T.nat; ++a) {
+        T.atom_task[a] = int(T.task.size());
+        const int b0 = T.atom_ent[a], cnt = T.atom_ent[a + 1] - b0;
+        for (int s = 0; s < cnt; s += len) T.task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
+    }
+    T.atom_task[T.nat] = int(T.task.size());
 }
 
 std::string table_key(const tdks_instance_desc &d) {
@@ -339,27 +364,31 @@ int upload(tdks_ctx *c, T **dst, const std::vector<T> &src) {
         if (r_ != TDKS_OK) return r_; \
     } while (0)
 
-// choose the column-segment length and block for one grid shape
-bool choose_tiling(const int N[3], int fp64, int want_block, int &zl, int &block) {
+// choose the column-segment length, block and occupancy target for one grid shape
+bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl, int &block, int &minw) {
     static const int zls[] = {2, 3, 4, 6, 8, 10, 12, 16};
     const int target = fp64 ? 4 : 8;
-    int best = -1, best_cost = 1 << 30;
+    int best_cost = 1 << 30;
+    bool found = false;
     for (int z : zls) {
         if (N[2] % z) continue;
         int b = N[0] * N[1] * (N[2] / z);
         b = (b + 63) / 64 * 64;
-        if (!propagate_config_ok(b, z)) continue;
+        // prefer 4 waves per SIMD for FP32 (two workgroups per CU), 2 for FP64 up to 512 threads
+        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : (fp64 ? 2 : 4));
+        if (!propagate_config_ok(b, z, w)) w = (w == 4) ? 2 : 4;
+        if (!propagate_config_ok(b, z, w)) continue;
         int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
         if (want_block > 0) cost = std::abs(b - want_block) * 16 + std::abs(z - target);
         if (cost < best_cost) {
             best_cost = cost;
-            best = z;
+            zl = z;
             block = b;
+            minw = w;
+            found = true;
         }
     }
-    if (best < 0) return false;
-    zl = best;
-    return true;
+    return found;
 }
 
 int sync_in(tdks_ctx *c) {
@@ -386,6 +415,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.dt = c->opt.dt;
     a.mode = mode;
     a.ng_max = S.ng_max;
+    a.ncol_max = S.ncol_max;
     a.nmaxd = S.nmaxd;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
@@ -399,7 +429,7 @@ int enqueue_step(tdks_ctx *c) {
     for (const ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
         a.work = c->d_work + S.wbeg;
-        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.nonorth, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
                          c->d_ctrs + 1, c->stream));
@@ -486,7 +516,7 @@ int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jds
         if (we <= wb) continue;
         PropArgs a = class_args(c, S, MODE_OBSERVE, c->d_Aobs, c->d_ctrs + 2);
         a.work = c->d_work + wb;
-        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.nonorth, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
                          c->stream));
@@ -599,15 +629,20 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
             ShapeClass S;
             for (int q = 0; q < 3; ++q) S.N[q] = I.N[q];
             S.nonorth = I.nonorth;
-            if (!choose_tiling(S.N, c->fp64, opt->block_size, S.zl, S.block))
+            if (!choose_tiling(S.N, c->fp64, opt->block_size, opt->waves_per_simd, S.zl, S.block, S.minw))
                 return fail(TDKS_E_UNSUPPORTED, "no built propagation tiling for grid %dx%dx%d", S.N[0], S.N[1], S.N[2]);
             c->classes.push_back(S);
             cls = int(c->classes.size()) - 1;
         }
         I.cls = cls;
         ShapeClass &S = c->classes[cls];
-        const TableSet &T = c->tables[I.table];
+        TableSet &T = c->tables[I.table];
+        if (T.cls < 0) {
+            T.cls = cls;
+            build_tasks(T, S.block);
+        }
         S.ng_max = std::max(S.ng_max, I.ng);
+        S.ncol_max = std::max(S.ncol_max, int(T.col_atom.size()));
         S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
         S.nat_max = std::max(S.nat_max, T.nat);
         S.ntask_max = std::max(S.ntask_max, int(T.task.size()));
@@ -655,11 +690,15 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_acopy, hipEventDisableTiming));
     for (TableSet &T : c->tables) {
+        CHK(upload(c, &T.d_col_atom, T.col_atom));
+        CHK(upload(c, &T.d_col_j01, T.col_j01));
         CHK(upload(c, &T.d_ent_pack, T.ent_pack));
         CHK(upload(c, &T.d_ent_g, T.ent_g));
+        CHK(upload(c, &T.d_ent_gf, T.ent_gf));
         CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
         CHK(upload(c, &T.d_pt_pack, T.pt_pack));
         CHK(upload(c, &T.d_pt_g, T.pt_g));
+        CHK(upload(c, &T.d_pt_gf, T.pt_gf));
         CHK(upload(c, &T.d_task, T.task));
         CHK(upload(c, &T.d_atom_task, T.atom_task));
         CHK(upload(c, &T.d_atom_tau, T.atom_tau));
@@ -720,11 +759,16 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.kcart = I.d_kcart;
         D.kw = I.d_kw;
         D.occ = I.d_occ;
+        D.ncol = int(T.col_atom.size());
+        D.col_atom = T.d_col_atom;
+        D.col_j01 = T.d_col_j01;
         D.ent_pack = T.d_ent_pack;
-        D.ent_g = T.d_ent_g;
+        D.ent_gf = T.d_ent_gf;
+        D.ent_gd = T.d_ent_g;
         D.pt_ptr = T.d_pt_ptr;
         D.pt_pack = T.d_pt_pack;
-        D.pt_g = T.d_pt_g;
+        D.pt_gf = T.d_pt_gf;
+        D.pt_gd = T.d_pt_g;
         D.task = T.d_task;
         D.atom_task = T.d_atom_task;
         D.atom_tau = T.d_atom_tau;
@@ -985,7 +1029,7 @@ int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, i
     a.work = c->d_work + I.wbeg;
     a.apply_in = win;
     a.apply_out = wout;
-    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.nonorth, c->stream));
+    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
     HIPCHK(launch_convert_out(wout, stage, n, c->fp64, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(hw, stage, 16 * n, where == TDKS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
@@ -1018,7 +1062,7 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
         for (const ShapeClass &S : c->classes) {
             PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
             a.work = c->d_work + S.wbeg;
-            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.nonorth, c->stream));
+            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
         }
         HIPCHK(hipEventRecord(ev[3 * s + 1], c->stream));
         HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
@@ -1047,8 +1091,10 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
     return rc;
 }
 
-int tdks_tiling(tdks_ctx *c, int *block, int *zl, int *bands_per_group, int *k_per_group, int *n_groups) {
+int tdks_tiling(tdks_ctx *c, int *block, int *zl, int *waves_per_simd, int *bands_per_group, int *k_per_group,
+                int *n_groups) {
     if (!c) return fail(TDKS_E_ARG, "null context");
+    if (waves_per_simd) *waves_per_simd = c->classes.empty() ? 0 : c->classes[0].minw;
     if (block) *block = c->classes.empty() ? 0 : c->classes[0].block;
     if (zl) *zl = c->classes.empty() ? 0 : c->classes[0].zl;
     if (bands_per_group) *bands_per_group = c->work.empty() ? 0 : c->work[0].nb;

@@ -45,8 +45,9 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(tdks_species), sizeof(tdks_instance_desc), sizeof(tdks_options));
   printf("%zu %zu %zu %zu\\n", offsetof(tdks_instance_desc, n_k), offsetof(tdks_instance_desc, group),
          offsetof(tdks_instance_desc, v_hxc_frozen), offsetof(tdks_instance_desc, species));
-  printf("%zu %zu %zu %zu\\n", offsetof(tdks_options, stream), offsetof(tdks_options, alloc_user),
-         offsetof(tdks_options, block_size), offsetof(tdks_options, graph_steps));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(tdks_options, stream), offsetof(tdks_options, alloc_user),
+         offsetof(tdks_options, block_size), offsetof(tdks_options, graph_steps),
+         offsetof(tdks_options, waves_per_simd));
   return 0;
 }
 """)
@@ -56,7 +57,8 @@ int main(void) {
     D, O = _lib.InstanceDesc, _lib.Options
     assert vals[:3] == [ctypes.sizeof(_lib.Species), ctypes.sizeof(D), ctypes.sizeof(O)]
     assert vals[3:7] == [D.n_k.offset, D.group.offset, D.v_hxc_frozen.offset, D.species.offset]
-    assert vals[7:11] == [O.stream.offset, O.alloc_user.offset, O.block_size.offset, O.graph_steps.offset]
+    assert vals[7:12] == [O.stream.offset, O.alloc_user.offset, O.block_size.offset, O.graph_steps.offset,
+                          O.waves_per_simd.offset]
 
 
 def test_default_options():
