@@ -135,6 +135,32 @@ __device__ __forceinline__ int opq(int x) {
     return x;
 }
 
+// Global-address-space view of a pointer read from device memory: lets the compiler
+// emit global (not flat) loads with a scalar base.
+#define TDKS_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const TDKS_GLOBAL T *gview(const T *p) {
+    return (const TDKS_GLOBAL T *)p;
+}
+template <typename T> __device__ __forceinline__ TDKS_GLOBAL T *gview_w(T *p) { return (TDKS_GLOBAL T *)p; }
+// two-component vector types go through clang native vectors for global loads/stores
+template <typename T> struct NV2;
+template <> struct NV2<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NV2<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NV2<int2> { typedef int type __attribute__((ext_vector_type(2))); };
+template <typename T> __device__ __forceinline__ T gld(const T *p) {
+    const auto v = *(const TDKS_GLOBAL typename NV2<T>::type *)p;
+    T r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+template <typename T> __device__ __forceinline__ void gst(T *p, T x) {
+    typename NV2<T>::type v;
+    v.x = x.x;
+    v.y = x.y;
+    *(TDKS_GLOBAL typename NV2<T>::type *)p = v;
+}
+
 template <typename R> __device__ __forceinline__ const R *gtab(const DevInst &I);
 template <> __device__ __forceinline__ const float *gtab<float>(const DevInst &I) { return I.ent_gf; }
 template <> __device__ __forceinline__ const double *gtab<double>(const DevInst &I) { return I.ent_gd; }
@@ -150,8 +176,15 @@ void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
     using Q4 = typename CT<R>::Q;
     extern __shared__ __align__(16) char smem[];
-    const WorkItem wi = a.work[blockIdx.x];
-    const DevInst &I = a.insts[wi.inst];
+    // the work item is uniform over the workgroup: keep it (and the instance) in scalar registers
+    const WorkItem *wp = a.work + blockIdx.x;
+    const int w_inst = __builtin_amdgcn_readfirstlane(wp->inst);
+    const int w_k0 = __builtin_amdgcn_readfirstlane(wp->k0);
+    const int w_nk = __builtin_amdgcn_readfirstlane(wp->nk);
+    const int w_b0 = __builtin_amdgcn_readfirstlane(wp->b0);
+    const int w_nb = __builtin_amdgcn_readfirstlane(wp->nb);
+    const int w_slot = __builtin_amdgcn_readfirstlane(wp->slot);
+    const DevInst &I = a.insts[w_inst];
     const int ng = I.ng;
     const int N0 = I.N[0], N1 = I.N[1], N2 = I.N[2];
     const int BS = blockDim.x;
@@ -171,9 +204,15 @@ void k_propagate(PropArgs a) {
     double *red = reinterpret_cast<double *>(smem + L.red);
     double *jsum = reinterpret_cast<double *>(smem + L.jacc);  // current partial of this workgroup
 
-    const R *vtot = reinterpret_cast<const R *>(I.vtot);
-    const R *gt = gtab<R>(I);
-    const R *pgt = ptgtab<R>(I);
+    const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
+    const auto *gt = gview(gtab<R>(I));
+    const auto *pgt = gview(ptgtab<R>(I));
+    const auto *ent_pack = gview(I.ent_pack);
+    const auto *pt_ptr = gview(I.pt_ptr);
+    const auto *pt_pack = gview(I.pt_pack);
+    const int2 *task = I.task;
+    const auto *atom_task = gview(I.atom_task);
+    const auto *kcart = gview(I.kcart);
     const int plane = N0 * N1;
     const int nseg = N2 / ZL;
     const bool active = tid < plane * nseg;
@@ -245,15 +284,15 @@ void k_propagate(PropArgs a) {
     const int norder = (a.mode == MODE_STEP) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
 
 #pragma unroll 1
-    for (int kk = 0; kk < wi.nk; ++kk) {
-        const int k = wi.k0 + kk;
+    for (int kk = 0; kk < w_nk; ++kk) {
+        const int k = w_k0 + kk;
         // kappa-dependent coefficients: -i kappa.grad_FD and |kappa|^2 / 2, kappa = k + A(t_n + dt/2)
         R b1[3], b2[3];
         R c0;
         {
             double km[3];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) km[d] = I.kcart[3 * k + d] + Am[d];
+            for (int d = 0; d < 3; ++d) km[d] = kcart[3 * k + d] + Am[d];
             const double kk2 = km[0] * km[0] + km[1] * km[1] + km[2] * km[2];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -270,8 +309,8 @@ void k_propagate(PropArgs a) {
         double km[3], ke[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            km[d] = I.kcart[3 * k + d] + Am[d];
-            ke[d] = I.kcart[3 * k + d] + Am[3 + d];
+            km[d] = kcart[3 * k + d] + Am[d];
+            ke[d] = kcart[3 * k + d] + Am[3 + d];
         }
         for (int c = tid; c < ncol; c += BS) {
             const int at = I.col_atom[c];
@@ -306,8 +345,8 @@ void k_propagate(PropArgs a) {
         }
 
 #pragma unroll 1
-        for (int bb = 0; bb < wi.nb; ++bb) {
-            const int b = wi.b0 + bb;
+        for (int bb = 0; bb < w_nb; ++bb) {
+            const int b = w_b0 + bb;
             const size_t orb = (size_t(k) * I.nb + b) * size_t(ng);
             C *ug = reinterpret_cast<C *>(I.u) + orb;
             const C *src = (a.mode == MODE_APPLY) ? reinterpret_cast<const C *>(a.apply_in) + orb : ug;
@@ -321,7 +360,7 @@ void k_propagate(PropArgs a) {
                 v.y = R(0);
                 if (active) {
                     const int p = pl + plane * z;
-                    v = src[p];
+                    v = gld(src + p);
                     W[p] = v;
                 }
                 acc[z] = v;
@@ -333,7 +372,7 @@ void k_propagate(PropArgs a) {
                 __syncthreads();  // W holds w_{m-1}
                 // ---- 1. projections c = <P|w> (atom-major tasks, one wave each)
                 for (int t = wave; t < ntask; t += NW) {
-                    const int2 tk = I.task[t];
+                    const int2 tk = gld(task + t);
                     const int e0 = tk.x, cnt = tk.y >> 8, at = tk.y & 255;
                     const Q4 ap = apar[at];
                     C s[4];
@@ -345,7 +384,7 @@ void k_propagate(PropArgs a) {
 #pragma unroll
                         for (int q = 0; q < kBatch; ++q) {
                             const int i = base + 64 * q;
-                            pk[q] = (i < cnt) ? I.ent_pack[e0 + i] : 0u;
+                            pk[q] = (i < cnt) ? ent_pack[e0 + i] : 0u;
                             gv[q] = (i < cnt) ? gt[e0 + i] : R(0);
                         }
 #pragma unroll
@@ -384,7 +423,7 @@ void k_propagate(PropArgs a) {
                     C s;
                     s.x = R(0);
                     s.y = R(0);
-                    for (int t = I.atom_task[at]; t < I.atom_task[at + 1]; ++t) {
+                    for (int t = atom_task[at]; t < atom_task[at + 1]; ++t) {
                         const C v = part[4 * t + l];
                         s.x += v.x;
                         s.y += v.y;
@@ -487,10 +526,10 @@ void k_propagate(PropArgs a) {
                         }
                     }
                     // non-local part: projector entries touching p
-                    const int e1 = I.pt_ptr[p + 1];
-                    for (int e = I.pt_ptr[p]; e < e1; ++e) {
+                    const int e1 = pt_ptr[p + 1];
+                    for (int e = pt_ptr[p]; e < e1; ++e) {
                         int pp, j2u, col;
-                        ent_unpack(I.pt_pack[e], pp, j2u, col);
+                        ent_unpack(pt_pack[e], pp, j2u, col);
                         const R gv = pgt[e];
                         const Q4 cd = cold[col];
                         const int at = int(cd.w);
@@ -515,7 +554,7 @@ void k_propagate(PropArgs a) {
                     C *out = reinterpret_cast<C *>(a.apply_out) + orb;
                     if (active) {
 #pragma unroll
-                        for (int z = 0; z < ZL; ++z) out[pw + plane * z] = hz[z];
+                        for (int z = 0; z < ZL; ++z) gst(out + pw + plane * z, hz[z]);
                     }
                 } else {
                     const R cm = R(a.dt / m);
@@ -541,7 +580,7 @@ void k_propagate(PropArgs a) {
                 for (int z = 0; z < ZL; ++z) {
                     const int p = ps + plane * z;
                     W[p] = acc[z];
-                    if (a.mode == MODE_STEP) ug[p] = acc[z];
+                    if (a.mode == MODE_STEP) gst(ug + p, acc[z]);
                 }
             }
             __syncthreads();
@@ -595,9 +634,9 @@ void k_propagate(PropArgs a) {
             double jnl[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
             for (int at = wave; at < nat; at += NW) {
-                const int e_beg = I.task[I.atom_task[at]].x;
-                const int tl = I.atom_task[at + 1] - 1;
-                const int e_end = I.task[tl].x + (I.task[tl].y >> 8);
+                const int e_beg = gld(task + atom_task[at]).x;
+                const int tl = atom_task[at + 1] - 1;
+                const int e_end = gld(task + tl).x + (gld(task + tl).y >> 8);
                 const double *par = I.atom_par + 4 * at;
                 const double ns = par[2], np = par[3];
                 double2 cs = make_double2(0.0, 0.0), cp[3], qq[6];
@@ -607,7 +646,7 @@ void k_propagate(PropArgs a) {
                 for (int i = 0; i < 6; ++i) qq[i] = make_double2(0.0, 0.0);
                 for (int e = e_beg + lane; e < e_end; e += 64) {
                     int p, j2u, col;
-                    ent_unpack(I.ent_pack[e], p, j2u, col);
+                    ent_unpack(ent_pack[e], p, j2u, col);
                     const double gv = double(gt[e]);
                     const Q4 cd = cold[col];
                     const double2 ph = cmul(cole[col], t2e[j2u]);
@@ -671,14 +710,14 @@ void k_propagate(PropArgs a) {
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     const double kin = dV * (I.c[0][q] * v7[0] + I.c[1][q] * v7[1] + I.c[2][q] * v7[2]);
-                    const double keq = I.kcart[3 * k + q] + Am[3 + q];
+                    const double keq = kcart[3 * k + q] + Am[3 + q];
                     jsum[q] += fo * (kin + keq * nrm + v7[4 + q]);
                 }
             }
         }
     }
     if (a.mode == MODE_APPLY) return;
-    double *rp = I.rho_part + size_t(wi.slot) * ng;
+    auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
     const int pr = opq(pbase + plane * z0);
     if (active) {
 #pragma unroll
@@ -686,7 +725,7 @@ void k_propagate(PropArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-        double *jp = I.j_part + 4 * wi.slot;
+        auto *jp = gview_w(I.j_part + 4 * w_slot);
         jp[0] = jsum[0];
         jp[1] = jsum[1];
         jp[2] = jsum[2];

@@ -287,13 +287,21 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                     }
                 }
         if (bycol.empty()) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
+        // entries of one atom in plane-major order (j2, then j1, j0): lanes that walk
+        // consecutive entries read consecutive grid points, i.e. distinct LDS banks
+        std::vector<std::pair<long long, Ent>> order;
         for (auto &kv : bycol) {
             const int col = int(T.col_atom.size());
             T.col_atom.push_back(a);
             T.col_j01.push_back(kv.first);
-            std::sort(kv.second.begin(), kv.second.end());
-            for (auto &e : kv.second) ents.push_back({col, e.first, e.second.first, e.second.second});
+            for (auto &e : kv.second) {
+                const long long key = (static_cast<long long>(e.first) << 16) | ((kv.first >> 8) << 8) | (kv.first & 255);
+                order.push_back({key, Ent{col, e.first, e.second.first, e.second.second}});
+            }
         }
+        std::sort(order.begin(), order.end(), [](const std::pair<long long, Ent> &x,
+                                                 const std::pair<long long, Ent> &y) { return x.first < y.first; });
+        for (auto &o : order) ents.push_back(o.second);
     }
     T.atom_ent[nat] = int(ents.size());
     if (T.col_atom.size() >= 4096)
@@ -327,8 +335,9 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
 void build_tasks(TableSet &T, int block) {
     const int nwaves = std::max(1, block / 64);
     const int total = T.atom_ent[T.nat];
+    // a multiple of 256 entries: each lane then loads whole batches of 4 entries
     int len = (total + 2 * nwaves - 1) / (2 * nwaves);
-    len = std::max(64, (len + 63) / 64 * 64);
+    len = std::max(256, (len + 255) / 256 * 256);
     T.task.clear();
     T.atom_task.assign(T.nat + 1, 0);
     for (int a = 0; a < T.nat; ++a) {
@@ -374,8 +383,8 @@ bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl
         if (N[2] % z) continue;
         int b = N[0] * N[1] * (N[2] / z);
         b = (b + 63) / 64 * 64;
-        // prefer 4 waves per SIMD for FP32 (two workgroups per CU), 2 for FP64 up to 512 threads
-        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : (fp64 ? 2 : 4));
+        // up to 512 threads: 2 waves per SIMD (256 registers, no spills) unless asked otherwise
+        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : 2);
         if (!propagate_config_ok(b, z, w)) w = (w == 4) ? 2 : 4;
         if (!propagate_config_ok(b, z, w)) continue;
         int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
