@@ -1,0 +1,76 @@
+"""Parity at the full size of the two-step workload (64 sub-simulations x 512 k x
+16 bands on 16^3, FP32 propagation), in the launch configuration the benchmark
+times.  The oracle cannot run the whole workload, so outputs are sampled:
+
+* density and v_Hxc of one sub-simulation after loading (its full k/band sum),
+* sampled orbitals after one step, propagated by the oracle one by one with the
+  oracle's v_Hxc of that sub-simulation,
+* the sub-simulation's current after one step (oracle over all its orbitals,
+  taken from the GPU's FP32 state),
+* bitwise equality of a sub-simulation inside the batch and alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import propagate as OP
+from oracle.hamiltonian import System
+from oracle.hxc import v_hxc as oracle_vhxc
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_two_step_full_size_sampled():
+    import torch
+    import paper_2112_00920_amd as tdks
+
+    wl = W.config("twostep_g16_mp8_s4")
+    insts = wl.instances
+    inst_id = 37
+    A = wl.field.table(1, wl.dt)
+    _say("full-size two-step FP32: loading 64 sub-simulations")
+    with tdks.Propagator(insts, precision="fp32", dt=wl.dt) as prop:
+        u_keep = None
+        for i, inst in enumerate(insts):
+            u = W.random_orbitals_torch(1000 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+            prop.load_orbitals(i, u)
+            if i == inst_id:
+                u_keep = u.cpu().numpy()
+            del u
+        til = prop.tiling()
+        rho0 = prop.density(inst_id)
+        vh0 = prop.vhxc(inst_id)
+        _say(f"  tiling {til}; one step")
+        prop.step(A)
+        dj = prop.current()[inst_id]
+        u1 = prop.get_orbitals(inst_id)
+    inst = insts[inst_id]
+    sysm = System(inst)
+    # the GPU loaded FP32-rounded orbitals: compare against the oracle on the same values
+    u32 = u_keep.astype(np.complex64).astype(np.complex128)
+    rho_o = OP.density(sysm, u32)
+    assert np.max(np.abs(rho0 - rho_o)) / np.max(rho_o) < 1e-12
+    v_o = oracle_vhxc(sysm.cell, rho_o)
+    assert np.max(np.abs(vh0 - v_o)) < 1e-11
+    _say("  density and v_Hxc after load match")
+    rng = np.random.default_rng(5)
+    for k in rng.choice(512, 6, replace=False):
+        kap = sysm.k_cart[k] + A[0, 0]
+        ref = OP.taylor_step(sysm, kap, v_o, u32[k], wl.dt)
+        err = np.max(np.abs(u1[k] - ref)) / np.max(np.abs(ref))
+        _say(f"  k {k}: orbital rel err {err:.2e}")
+        assert err < 2e-6
+    # current of the sub-simulation from the GPU state after the step (FP64 oracle arithmetic)
+    J1 = OP.current(sysm, A[0, 1], u1)
+    J0 = OP.current(sysm, np.zeros(3), u32)
+    ref = J1 - J0
+    err = np.max(np.abs(dj[0] - ref))
+    _say(f"  current: |dJ_gpu - dJ_oracle(gpu state)| = {err:.2e}, |dJ| = {np.max(np.abs(ref)):.2e}")
+    assert err < 1e-12 + 1e-6 * np.max(np.abs(ref))

@@ -231,3 +231,68 @@ def test_diamond8_g12_mp2_fp64(tdks):
     err = np.max(np.abs(dj[0] - dj_o)) / np.max(np.abs(dj_o))
     _say(f"  tiling {til} dJ err {err:.2e}")
     assert err < 1e-10
+
+
+def test_pulse_time_varying_field(tdks):
+    """sin^2 pulse: A(t_n + dt/2) != A(t_{n+1}), so propagation and current use different kappa."""
+    _say("sin^2 pulse, FP64 and FP32")
+    inst = W.make_instance("diamond8", (8, 8, 8), 3, [species()], W.KSpec((2, 1, 1), (2, 2, 2), (1, 0, 1)))
+    u0 = W.random_orbitals(31, 2, 3, inst.grid, inst.omega)
+    fld = W.Field("pulse", direction=(0.6, 0.0, 0.8), A0=0.5, omega=0.3, T=0.4)
+    A = fld.table(16, 0.02)
+    assert np.max(np.abs(A[:, 0] - A[:, 1])) > 1e-3
+    dj_o, u_o, rho_o, _ = run_oracle(inst, u0, A)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        dj, us, rhos, _, _ = run_gpu(tdks, [inst], [u0], A, prec)
+        err = np.max(np.abs(dj[0] - dj_o)) / np.max(np.abs(dj_o))
+        _say(f"  {prec} dJ err {err:.2e}")
+        assert err < tol
+
+
+def test_uneven_batch_one_context(tdks):
+    """fcc2 (61-point stencil), cubic cells on two grids and a 1x1x2 supercell in one context."""
+    _say("uneven batch")
+    sp = species(5)
+    insts = [
+        W.make_instance("fcc2", (8, 8, 8), 4, [sp], W.KSpec((2, 2, 2)), group=0),
+        W.make_instance("diamond8", (8, 8, 8), 5, [sp], W.KSpec((2, 1, 1), (2, 2, 2), (1, 1, 0)), group=1),
+        W.make_instance("diamond8", (10, 10, 10), 5, [sp], W.KSpec((2, 1, 1), (2, 2, 2), (0, 1, 1)), group=1),
+        W.make_instance("super16", (8, 8, 16), 6, [sp], W.KSpec((1, 1, 2)), group=2),
+    ]
+    u0s = [W.random_orbitals(40 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega) for i, inst in enumerate(insts)]
+    A = W.Field("kick", 1e-3).table(5, 0.02)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        with tdks.Propagator(insts, precision=prec) as prop:
+            for i, u in enumerate(u0s):
+                prop.load_orbitals(i, u)
+            prop.step(A)
+            dj = prop.current()
+            djg = prop.current(per="group")
+        refs = []
+        for i, inst in enumerate(insts):
+            dj_o, _, _, _ = run_oracle(inst, u0s[i], A)
+            refs.append(dj_o)
+            err = np.max(np.abs(dj[i] - dj_o)) / np.max(np.abs(dj_o))
+            _say(f"  {prec} instance {i} ({inst.cell} {inst.grid}) dJ err {err:.2e}")
+            assert err < tol
+        np.testing.assert_allclose(djg[1], 0.5 * (dj[1] + dj[2]), rtol=1e-13, atol=1e-20)
+
+
+def test_eigenstate_norm_closed_form_on_gpu(tdks):
+    """Orbitals that are eigenvectors of the dense h lose norm per step as |T4(-i eps dt)|^2."""
+    _say("eigenstate norm")
+    inst = W.make_instance("diamond8", (6, 6, 6), 3, [species()], W.KSpec((1, 1, 1)))
+    sysm = System(inst)
+    H = sysm.dense_h(sysm.k_cart[0], 0.0)
+    e, vec = np.linalg.eigh(0.5 * (H + H.conj().T))
+    sel = [0, 100, 215]
+    u0 = (vec[:, sel].T / np.sqrt(sysm.cell.dV)).reshape(1, 3, 6, 6, 6)
+    dt, n = 0.05, 10
+    A = np.zeros((n, 2, 3))
+    with tdks.Propagator([inst], precision="fp64", dt=dt, hxc_mode="none") as prop:
+        prop.load_orbitals(0, u0)
+        prop.step(A)
+        nr = prop.norms(0)[0]
+    for j, s in enumerate(sel):
+        x = e[s] * dt
+        assert abs(nr[j] - (1 - x ** 6 / 72 + x ** 8 / 576) ** n) < 1e-12
