@@ -39,6 +39,8 @@ struct DevInst {
     const float *ent_gf;       // radial factor g(|d|) of each entry, FP32 copy
     const double *ent_gd;      // ... FP64 copy
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
+    const uint16_t *pt_ptr16;  // same, 16-bit copy (staged into LDS by the FP32 kernel)
+    int nent;                  // projector entries
     const uint32_t *pt_pack;   // point-major copy of ent_pack
     const float *pt_gf;
     const double *pt_gd;
@@ -76,6 +78,7 @@ struct PropArgs {
     int mode;
     int ng_max;            // largest grid of the launch (sizes the LDS orbital buffer)
     int ncol_max;          // most projector column images of an instance in the launch
+    int nent_max;          // most projector entries of an instance in the launch
     int nmaxd;             // largest N_d of the launch (phase tables)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
@@ -85,8 +88,8 @@ struct PropArgs {
 
 // Host-side launchers implemented in tdks_kernels.hip.
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
-                            int nonorth, hipStream_t s);
-size_t propagate_lds_bytes(int fp64, const PropArgs &a, int block);
+                            int nonorth, int sl, hipStream_t s);
+size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block);
 bool propagate_config_ok(int block, int zl, int minw);
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
                          double *jout, int jstride, const int *rec_ctr, hipStream_t s);

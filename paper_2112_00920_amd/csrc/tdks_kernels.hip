@@ -4,13 +4,13 @@
 
 namespace tdks {
 
-hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, int, int, hipStream_t);
 
-size_t propagate_lds_bytes(int fp64, const PropArgs &a, int block) {
-    return propagate_lds_bytes_inl(fp64, a, block);
+size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block) {
+    return propagate_lds_bytes_inl(fp64, sl, a, block);
 }
 
 bool propagate_config_ok(int block, int zl, int minw) {
@@ -22,12 +22,12 @@ bool propagate_config_ok(int block, int zl, int minw) {
 }
 
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
-                            int nonorth, hipStream_t s) {
+                            int nonorth, int sl, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, minw, s)
-                             : launch_propagate_f64_orth(a, n_items, block, zl, minw, s);
-    return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, minw, s)
-                   : launch_propagate_f32_orth(a, n_items, block, zl, minw, s);
+    if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, minw, sl, s)
+                             : launch_propagate_f64_orth(a, n_items, block, zl, minw, sl, s);
+    return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, minw, sl, s)
+                   : launch_propagate_f32_orth(a, n_items, block, zl, minw, sl, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -55,6 +55,47 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Sum over the 64 lanes of a wave with DPP moves (VALU latency, no LDS round trips):
+// quad all-reduce, half-row and row mirrors give every lane its row sum; row_bcast:15
+// and row_bcast:31 then fold the rows so that lane 63 holds the total, which is
+// broadcast with readlane.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __builtin_bit_cast(float, dpp_i<CTRL, ROWMASK>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_i<CTRL, ROWMASK>(int(b & 0xffffffffll));
+    const int hi = dpp_i<CTRL, ROWMASK>(int(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ float wave_total(float v) {
+    v += dpp_f<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double wave_total(double v) {
+    v += dpp_d<0xB1, 0xF>(v);
+    v += dpp_d<0x4E, 0xF>(v);
+    v += dpp_d<0x141, 0xF>(v);
+    v += dpp_d<0x140, 0xF>(v);
+    v += dpp_d<0x142, 0xA>(v);
+    v += dpp_d<0x143, 0xC>(v);
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // 4th-order central differences (+-2 neighbours)
 #define D1C1 (2.0 / 3.0)
 #define D1C2 (-1.0 / 12.0)
@@ -71,13 +112,13 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, ptp, ptk, ptg, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline PropLds prop_lds(int fp64, int ng_max, int ncol_max, int nmaxd, int nat_max,
-                                            int ntask_max, int block) {
+__host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
+                                            int nmaxd, int nat_max, int ntask_max, int block) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
@@ -95,12 +136,16 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int ng_max, int ncol_max, 
     L.ec = o; o = al16(o + c * 4 * na);
     L.red = o; o = al16(o + 8 * 8 * (block / 64 + 1));
     L.jacc = o; o = al16(o + 8 * 4);
+    // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
+    L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
+    L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
+    L.ptg = o; o = al16(o + (sl ? r * size_t(nent_max) : 0));
     L.total = o;
     return L;
 }
 
-inline size_t propagate_lds_bytes_inl(int fp64, const PropArgs &a, int block) {
-    return prop_lds(fp64, a.ng_max, a.ncol_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
+inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
+    return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
 }
 
 // Block-wide sum of K <= 8 doubles held by every thread; every thread receives the sums.
@@ -109,7 +154,7 @@ template <int K>
 __device__ __forceinline__ void block_sum(double *v, double *red, int nwaves) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
+    for (int i = 0; i < K; ++i) v[i] = wave_total(v[i]);
     __syncthreads();
     if (lane == 0) {
 #pragma unroll
@@ -170,7 +215,7 @@ template <> __device__ __forceinline__ const double *ptgtab<double>(const DevIns
 
 constexpr int kBatch = 4;  // projector entries a lane loads before using them
 
-template <typename R, int ZL, bool NONORTH, int MAXT, int MINW>
+template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -191,7 +236,8 @@ void k_propagate(PropArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = BS >> 6;
 
-    const PropLds L = prop_lds(sizeof(R) == 8, a.ng_max, a.ncol_max, a.nmaxd, a.nat_max, a.ntask_max, BS);
+    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max,
+                               a.ntask_max, BS);
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
     C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
@@ -203,6 +249,9 @@ void k_propagate(PropArgs a) {
     C *EC = reinterpret_cast<C *>(smem + L.ec);
     double *red = reinterpret_cast<double *>(smem + L.red);
     double *jsum = reinterpret_cast<double *>(smem + L.jacc);  // current partial of this workgroup
+    uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
+    uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
+    R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
     const auto *gt = gview(gtab<R>(I));
@@ -259,6 +308,15 @@ void k_propagate(PropArgs a) {
         q.z = R(par[2]);
         q.w = R(par[3]);
         apar[at] = q;
+    }
+
+    if (SL) {
+        const auto *p16 = gview(I.pt_ptr16);
+        for (int i = tid; i <= ng; i += BS) ptp_l[i] = p16[i];
+        for (int e = tid; e < I.nent; e += BS) {
+            ptk_l[e] = pt_pack[e];
+            ptg_l[e] = pgt[e];
+        }
     }
 
     R vz[ZL];
@@ -409,8 +467,8 @@ void k_propagate(PropArgs a) {
                     }
 #pragma unroll
                     for (int l = 0; l < 4; ++l) {
-                        s[l].x = wave_sum(s[l].x);
-                        s[l].y = wave_sum(s[l].y);
+                        s[l].x = wave_total(s[l].x);
+                        s[l].y = wave_total(s[l].y);
                     }
                     if (lane == 0) {
 #pragma unroll
@@ -526,11 +584,12 @@ void k_propagate(PropArgs a) {
                         }
                     }
                     // non-local part: projector entries touching p
-                    const int e1 = pt_ptr[p + 1];
-                    for (int e = pt_ptr[p]; e < e1; ++e) {
+                    const int e0s = SL ? int(ptp_l[p]) : pt_ptr[p];
+                    const int e1 = SL ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
+                    for (int e = e0s; e < e1; ++e) {
                         int pp, j2u, col;
-                        ent_unpack(pt_pack[e], pp, j2u, col);
-                        const R gv = pgt[e];
+                        ent_unpack(SL ? ptk_l[e] : pt_pack[e], pp, j2u, col);
+                        const R gv = SL ? ptg_l[e] : pgt[e];
                         const Q4 cd = cold[col];
                         const int at = int(cd.w);
                         const Q4 ap = apar[at];
@@ -674,17 +733,17 @@ void k_propagate(PropArgs a) {
                     qq[4].x += q02 * x.x; qq[4].y += q02 * x.y;
                     qq[5].x += q12 * x.x; qq[5].y += q12 * x.y;
                 }
-                cs.x = wave_sum(cs.x);
-                cs.y = wave_sum(cs.y);
+                cs.x = wave_total(cs.x);
+                cs.y = wave_total(cs.y);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    cp[i].x = wave_sum(cp[i].x);
-                    cp[i].y = wave_sum(cp[i].y);
+                    cp[i].x = wave_total(cp[i].x);
+                    cp[i].y = wave_total(cp[i].y);
                 }
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
-                    qq[i].x = wave_sum(qq[i].x);
-                    qq[i].y = wave_sum(qq[i].y);
+                    qq[i].x = wave_total(qq[i].x);
+                    qq[i].y = wave_total(qq[i].y);
                 }
                 const double Es = par[0], Ep = par[1];
                 const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};

@@ -50,6 +50,7 @@ struct TableSet {
     std::vector<double> ent_g, pt_g;
     std::vector<float> ent_gf, pt_gf;
     std::vector<int> pt_ptr, atom_task, atom_ent;  // atom_ent: [nat+1] first entry of each atom
+    std::vector<uint16_t> pt_ptr16;
     std::vector<int2> task;
     std::vector<double> atom_tau, atom_par;
     int nat = 0;
@@ -60,6 +61,7 @@ struct TableSet {
     double *d_ent_g = nullptr, *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
     float *d_ent_gf = nullptr, *d_pt_gf = nullptr;
     int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
+    uint16_t *d_pt_ptr16 = nullptr;
     int2 *d_task = nullptr;
 };
 
@@ -85,9 +87,9 @@ struct InstHost {
 struct ShapeClass {
     int N[3];
     bool nonorth;
-    int zl = 0, block = 0, minw = 0;
+    int zl = 0, block = 0, minw = 0, sl = 0;
     int wbeg = 0, wend = 0;
-    int ng_max = 0, ncol_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
+    int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
 };
 
 }  // namespace
@@ -326,23 +328,25 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         }
     }
     T.pt_ptr[I.ng] = int(T.pt_pack.size());
+    if (T.pt_pack.size() > 65535) return fail(TDKS_E_UNSUPPORTED, "more than 65535 projector entries");
+    T.pt_ptr16.assign(T.pt_ptr.begin(), T.pt_ptr.end());
     T.ent_gf.assign(T.ent_g.begin(), T.ent_g.end());
     T.pt_gf.assign(T.pt_g.begin(), T.pt_g.end());
     return TDKS_OK;
 }
 
-// projection tasks: contiguous entry ranges of one atom, about two per wave of the block
+// projection tasks: contiguous entry ranges of one atom, sized so that the block's waves
+// get about one task each (one wave reduction per task)
 void build_tasks(TableSet &T, int block) {
     const int nwaves = std::max(1, block / 64);
-    const int total = T.atom_ent[T.nat];
-    // a multiple of 256 entries: each lane then loads whole batches of 4 entries
-    int len = (total + 2 * nwaves - 1) / (2 * nwaves);
-    len = std::max(256, (len + 255) / 256 * 256);
+    const long long total = std::max(1, T.atom_ent[T.nat]);
     T.task.clear();
     T.atom_task.assign(T.nat + 1, 0);
     for (int a = 0; a < T.nat; ++a) {
         T.atom_task[a] = int(T.task.size());
         const int b0 = T.atom_ent[a], cnt = T.atom_ent[a + 1] - b0;
+        const int nt = std::max(1, int((nwaves * (long long)cnt + total / 2) / total));
+        const int len = (cnt + nt - 1) / nt;
         for (int s = 0; s < cnt; s += len) T.task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
     }
     T.atom_task[T.nat] = int(T.task.size());
@@ -425,6 +429,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.mode = mode;
     a.ng_max = S.ng_max;
     a.ncol_max = S.ncol_max;
+    a.nent_max = S.nent_max;
     a.nmaxd = S.nmaxd;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
@@ -438,7 +443,7 @@ int enqueue_step(tdks_ctx *c) {
     for (const ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
         a.work = c->d_work + S.wbeg;
-        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
                          c->d_ctrs + 1, c->stream));
@@ -525,7 +530,7 @@ int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jds
         if (we <= wb) continue;
         PropArgs a = class_args(c, S, MODE_OBSERVE, c->d_Aobs, c->d_ctrs + 2);
         a.work = c->d_work + wb;
-        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
                          c->stream));
@@ -652,13 +657,16 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         }
         S.ng_max = std::max(S.ng_max, I.ng);
         S.ncol_max = std::max(S.ncol_max, int(T.col_atom.size()));
+        S.nent_max = std::max(S.nent_max, int(T.ent_pack.size()));
         S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
         S.nat_max = std::max(S.nat_max, T.nat);
         S.ntask_max = std::max(S.ntask_max, int(T.task.size()));
     }
     for (ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
-        const size_t lds = propagate_lds_bytes(c->fp64, a, S.block);
+        // FP32: stage the point-major projector tables in LDS when they fit
+        S.sl = (!c->fp64 && propagate_lds_bytes(c->fp64, 1, a, S.block) <= 160 * 1024) ? 1 : 0;
+        const size_t lds = propagate_lds_bytes(c->fp64, S.sl, a, S.block);
         if (lds > 160 * 1024)
             return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of LDS per workgroup", S.N[0], S.N[1],
                         S.N[2], lds);
@@ -705,6 +713,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         CHK(upload(c, &T.d_ent_g, T.ent_g));
         CHK(upload(c, &T.d_ent_gf, T.ent_gf));
         CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
+        CHK(upload(c, &T.d_pt_ptr16, T.pt_ptr16));
         CHK(upload(c, &T.d_pt_pack, T.pt_pack));
         CHK(upload(c, &T.d_pt_g, T.pt_g));
         CHK(upload(c, &T.d_pt_gf, T.pt_gf));
@@ -775,6 +784,8 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.ent_gf = T.d_ent_gf;
         D.ent_gd = T.d_ent_g;
         D.pt_ptr = T.d_pt_ptr;
+        D.pt_ptr16 = T.d_pt_ptr16;
+        D.nent = int(T.ent_pack.size());
         D.pt_pack = T.d_pt_pack;
         D.pt_gf = T.d_pt_gf;
         D.pt_gd = T.d_pt_g;
@@ -1038,7 +1049,7 @@ int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, i
     a.work = c->d_work + I.wbeg;
     a.apply_in = win;
     a.apply_out = wout;
-    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
+    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
     HIPCHK(launch_convert_out(wout, stage, n, c->fp64, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(hw, stage, 16 * n, where == TDKS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
@@ -1071,7 +1082,7 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
         for (const ShapeClass &S : c->classes) {
             PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
             a.work = c->d_work + S.wbeg;
-            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, c->stream));
+            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
         }
         HIPCHK(hipEventRecord(ev[3 * s + 1], c->stream));
         HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
