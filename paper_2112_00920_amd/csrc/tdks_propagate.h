@@ -112,7 +112,7 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, ptp, ptk, ptg, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, ptp, ptk, ptg, rho, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -140,6 +140,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
     L.ptg = o; o = al16(o + (sl ? r * size_t(nent_max) : 0));
+    L.rho = o; o = al16(o + 8 * size_t(ng_max));  // FP64 density partial of the workgroup
     L.total = o;
     return L;
 }
@@ -170,6 +171,18 @@ __device__ __forceinline__ void block_sum(double *v, double *red, int nwaves) {
 #pragma unroll
     for (int i = 0; i < K; ++i) v[i] = red[nwaves * K + i];
     __syncthreads();
+}
+
+// Uniform real value forced into a scalar register (VALU instructions then read it as
+// their scalar operand instead of holding a copy per lane).
+__device__ __forceinline__ float uni(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uni(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
 // Opaque copy of a value: stops loop-invariant code motion from hoisting address
@@ -252,6 +265,7 @@ void k_propagate(PropArgs a) {
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
     uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
     R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
+    double *RHO = reinterpret_cast<double *>(smem + L.rho);
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
     const auto *gt = gview(gtab<R>(I));
@@ -285,7 +299,7 @@ void k_propagate(PropArgs a) {
     const int nat = I.nat;
     const int ntask = I.ntask;
     const int ncol = I.ncol;
-    const R h2x = R(I.hv[2][0]), h2y = R(I.hv[2][1]), h2z = R(I.hv[2][2]);
+    const R h2x = uni(R(I.hv[2][0])), h2y = uni(R(I.hv[2][1])), h2z = uni(R(I.hv[2][2]));
 
     // k-independent projector geometry of this instance into LDS
     for (int c = tid; c < ncol; c += BS) {
@@ -320,11 +334,10 @@ void k_propagate(PropArgs a) {
     }
 
     R vz[ZL];
-    double rho[ZL];
 #pragma unroll
     for (int z = 0; z < ZL; ++z) {
         vz[z] = active ? vtot[pbase + plane * (z0 + z)] : R(0);
-        rho[z] = 0.0;
+        if (active) RHO[pbase + plane * (z0 + z)] = 0.0;
     }
 
     // Laplacian coefficients (metric only)
@@ -332,13 +345,13 @@ void k_propagate(PropArgs a) {
     double c0l = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        a1[d] = R(-0.5 * I.g[d][d] * D2C1);
-        a2[d] = R(-0.5 * I.g[d][d] * D2C2);
+        a1[d] = uni(R(-0.5 * I.g[d][d] * D2C1));
+        a2[d] = uni(R(-0.5 * I.g[d][d] * D2C2));
         c0l += -0.5 * I.g[d][d] * D2C0;
     }
-    cx[0] = R(-I.g[0][1]);  // -(1/2) * 2 g_de for d < e
-    cx[1] = R(-I.g[0][2]);
-    cx[2] = R(-I.g[1][2]);
+    cx[0] = uni(R(-I.g[0][1]));  // -(1/2) * 2 g_de for d < e
+    cx[1] = uni(R(-I.g[0][2]));
+    cx[2] = uni(R(-I.g[1][2]));
     const int norder = (a.mode == MODE_STEP) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
 
 #pragma unroll 1
@@ -355,10 +368,10 @@ void k_propagate(PropArgs a) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double kc = km[0] * I.c[d][0] + km[1] * I.c[d][1] + km[2] * I.c[d][2];
-                b1[d] = R(kc * D1C1);
-                b2[d] = R(kc * D1C2);
+                b1[d] = uni(R(kc * D1C1));
+                b2[d] = uni(R(kc * D1C2));
             }
-            c0 = R(c0l + 0.5 * kk2);
+            c0 = uni(R(c0l + 0.5 * kk2));
         }
 
         // phases: column images and the a_3 factor, for kappa(t_n + dt/2) and kappa(t_{n+1})
@@ -644,7 +657,8 @@ void k_propagate(PropArgs a) {
             }
             __syncthreads();
             const double fo = I.kw[k] * I.occ[b];
-            double qn[4] = {0.0, 0.0, 0.0, 0.0};  // Q_d = sum Im(conj(u) D1_d u), and sum |u|^2
+            // per-thread sums over the owned points in the orbital precision, FP64 beyond
+            R qn[4] = {R(0), R(0), R(0), R(0)};  // Q_d = sum Im(conj(u) D1_d u), and sum |u|^2
             const int pk0 = opq(pbase);
             int oxk[4], oyk[4];
 #pragma unroll
@@ -658,9 +672,8 @@ void k_propagate(PropArgs a) {
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
                     const C u = W[p];
-                    const double ux = double(u.x), uy = double(u.y);
-                    const double n2 = ux * ux + uy * uy;
-                    rho[z] += fo * n2;
+                    const R n2 = u.x * u.x + u.y * u.y;
+                    RHO[p] += fo * double(n2);  // own point: no other thread touches it
                     qn[3] += n2;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
@@ -680,10 +693,9 @@ void k_propagate(PropArgs a) {
                         }
                         const C p1 = W[p + o[0]], m1 = W[p + o[1]];
                         const C p2 = W[p + o[2]], m2 = W[p + o[3]];
-                        // D1 in the orbital precision, the products accumulated in FP64
                         const R dx = R(D1C1) * (p1.x - m1.x) + R(D1C2) * (p2.x - m2.x);
                         const R dy = R(D1C1) * (p1.y - m1.y) + R(D1C2) * (p2.y - m2.y);
-                        qn[d] += ux * double(dy) - uy * double(dx);
+                        qn[d] += u.x * dy - u.y * dx;
                     }
                 }
             }
@@ -698,63 +710,66 @@ void k_propagate(PropArgs a) {
                 const int e_end = gld(task + tl).x + (gld(task + tl).y >> 8);
                 const double *par = I.atom_par + 4 * at;
                 const double ns = par[2], np = par[3];
-                double2 cs = make_double2(0.0, 0.0), cp[3], qq[6];
+                // per-lane moment sums in the orbital precision (products of orbital values),
+                // cross-lane totals and everything after them in FP64
+                C cs, cp[3], qq[6];
+                cs.x = R(0);
+                cs.y = R(0);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) cp[i] = make_double2(0.0, 0.0);
+                for (int i = 0; i < 3; ++i) { cp[i].x = R(0); cp[i].y = R(0); }
 #pragma unroll
-                for (int i = 0; i < 6; ++i) qq[i] = make_double2(0.0, 0.0);
+                for (int i = 0; i < 6; ++i) { qq[i].x = R(0); qq[i].y = R(0); }
+                const R rns = R(ns), rnp = R(np);
                 for (int e = e_beg + lane; e < e_end; e += 64) {
                     int p, j2u, col;
                     ent_unpack(ent_pack[e], p, j2u, col);
-                    const double gv = double(gt[e]);
+                    const R gv = gt[e];
                     const Q4 cd = cold[col];
-                    const double2 ph = cmul(cole[col], t2e[j2u]);
-                    const C wv = W[p];
-                    const double2 x = cmul(ph, make_double2(double(wv.x), double(wv.y)));
-                    const double j2 = double(j2u - N2);
-                    const double d[3] = {double(cd.x) + j2 * I.hv[2][0], double(cd.y) + j2 * I.hv[2][1],
-                                         double(cd.z) + j2 * I.hv[2][2]};
-                    const double fs = ns * gv, fp = np * gv;
+                    const double2 phd = cmul(cole[col], t2e[j2u]);
+                    C ph;
+                    ph.x = R(phd.x);
+                    ph.y = R(phd.y);
+                    const C x = cmul(ph, W[p]);
+                    const R j2 = R(j2u - N2);
+                    const R d0 = cd.x + j2 * h2x, d1 = cd.y + j2 * h2y, d2 = cd.z + j2 * h2z;
+                    const R fs = rns * gv, fp = rnp * gv;
                     cs.x += fs * x.x;
                     cs.y += fs * x.y;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const double f = fp * d[i];
-                        cp[i].x += f * x.x;
-                        cp[i].y += f * x.y;
-                    }
+                    const R f0 = fp * d0, f1 = fp * d1, f2 = fp * d2;
+                    cp[0].x += f0 * x.x; cp[0].y += f0 * x.y;
+                    cp[1].x += f1 * x.x; cp[1].y += f1 * x.y;
+                    cp[2].x += f2 * x.x; cp[2].y += f2 * x.y;
                     // Q_ij, i <= j: 00 11 22 01 02 12
-                    const double q00 = fp * d[0] * d[0], q11 = fp * d[1] * d[1], q22 = fp * d[2] * d[2];
-                    const double q01 = fp * d[0] * d[1], q02 = fp * d[0] * d[2], q12 = fp * d[1] * d[2];
-                    qq[0].x += q00 * x.x; qq[0].y += q00 * x.y;
-                    qq[1].x += q11 * x.x; qq[1].y += q11 * x.y;
-                    qq[2].x += q22 * x.x; qq[2].y += q22 * x.y;
-                    qq[3].x += q01 * x.x; qq[3].y += q01 * x.y;
-                    qq[4].x += q02 * x.x; qq[4].y += q02 * x.y;
-                    qq[5].x += q12 * x.x; qq[5].y += q12 * x.y;
+                    qq[0].x += f0 * d0 * x.x; qq[0].y += f0 * d0 * x.y;
+                    qq[1].x += f1 * d1 * x.x; qq[1].y += f1 * d1 * x.y;
+                    qq[2].x += f2 * d2 * x.x; qq[2].y += f2 * d2 * x.y;
+                    qq[3].x += f0 * d1 * x.x; qq[3].y += f0 * d1 * x.y;
+                    qq[4].x += f0 * d2 * x.x; qq[4].y += f0 * d2 * x.y;
+                    qq[5].x += f1 * d2 * x.x; qq[5].y += f1 * d2 * x.y;
                 }
-                cs.x = wave_total(cs.x);
-                cs.y = wave_total(cs.y);
+                double2 tcs, tcp[3], tqq[6];
+                tcs.x = wave_total(double(cs.x));
+                tcs.y = wave_total(double(cs.y));
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    cp[i].x = wave_total(cp[i].x);
-                    cp[i].y = wave_total(cp[i].y);
+                    tcp[i].x = wave_total(double(cp[i].x));
+                    tcp[i].y = wave_total(double(cp[i].y));
                 }
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
-                    qq[i].x = wave_total(qq[i].x);
-                    qq[i].y = wave_total(qq[i].y);
+                    tqq[i].x = wave_total(double(qq[i].x));
+                    tqq[i].y = wave_total(double(qq[i].y));
                 }
                 const double Es = par[0], Ep = par[1];
                 const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
                     // s channel: c_{d_j,s} = (N_s/N_p) c_{p,j}
-                    double v = Es * (ns / np) * (cp[j].x * cs.y - cp[j].y * cs.x);
+                    double v = Es * (ns / np) * (tcp[j].x * tcs.y - tcp[j].y * tcs.x);
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
-                        const double2 qv = qq[qi[i][j]];
-                        v += Ep * (qv.x * cp[i].y - qv.y * cp[i].x);
+                        const double2 qv = tqq[qi[i][j]];
+                        v += Ep * (qv.x * tcp[i].y - qv.y * tcp[i].x);
                     }
                     jnl[j] += 2.0 * dV * dV * v;
                 }
@@ -762,7 +777,7 @@ void k_propagate(PropArgs a) {
             if (lane != 0) {
                 jnl[0] = jnl[1] = jnl[2] = 0.0;
             }
-            double v7[7] = {qn[0], qn[1], qn[2], qn[3], jnl[0], jnl[1], jnl[2]};
+            double v7[7] = {double(qn[0]), double(qn[1]), double(qn[2]), double(qn[3]), jnl[0], jnl[1], jnl[2]};
             block_sum<7>(v7, red, NW);
             if (tid == 0) {
                 const double nrm = v7[3] * dV;
@@ -780,7 +795,7 @@ void k_propagate(PropArgs a) {
     const int pr = opq(pbase + plane * z0);
     if (active) {
 #pragma unroll
-        for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = rho[z];
+        for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = RHO[pr + plane * z];
     }
     __syncthreads();
     if (tid == 0) {

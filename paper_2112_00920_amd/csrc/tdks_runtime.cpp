@@ -380,15 +380,16 @@ int upload(tdks_ctx *c, T **dst, const std::vector<T> &src) {
 // choose the column-segment length, block and occupancy target for one grid shape
 bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl, int &block, int &minw) {
     static const int zls[] = {2, 3, 4, 6, 8, 10, 12, 16};
-    const int target = fp64 ? 4 : 8;
+    // measured on MI355X: FP32 runs best with short segments and 4 waves per SIMD,
+    // FP64 with 512-thread blocks at 2 waves per SIMD (see the autotuner for other shapes)
+    const int target = fp64 ? 8 : 4;
     int best_cost = 1 << 30;
     bool found = false;
     for (int z : zls) {
         if (N[2] % z) continue;
         int b = N[0] * N[1] * (N[2] / z);
         b = (b + 63) / 64 * 64;
-        // up to 512 threads: 2 waves per SIMD (256 registers, no spills) unless asked otherwise
-        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : 2);
+        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : (fp64 ? 2 : 4));
         if (!propagate_config_ok(b, z, w)) w = (w == 4) ? 2 : 4;
         if (!propagate_config_ok(b, z, w)) continue;
         int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
