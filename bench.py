@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="two-step sub-simulations (64 = full workload)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB -> 1 GiB device copy kernel (torch neg), so that a counter "
+                         "profile of this command holds a kernel of known HBM traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the two-step sub-simulations "
@@ -140,6 +143,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     K, Wm = args.steps, args.warmup
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x neg over 2^28 floats (1 GiB read + 1 GiB written per launch)")
     wl, insts = make_two_step(args.instances)
     A = wl.field.table(K + Wm + 8, wl.dt)
     n_inst = len(insts)

@@ -672,9 +672,9 @@ void k_propagate(PropArgs a) {
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
                     const C u = W[p];
-                    const R n2 = u.x * u.x + u.y * u.y;
-                    RHO[p] += fo * double(n2);  // own point: no other thread touches it
-                    qn[3] += n2;
+                    const double ux = double(u.x), uy = double(u.y);
+                    RHO[p] += fo * (ux * ux + uy * uy);  // own point: no other thread touches it
+                    qn[3] += u.x * u.x + u.y * u.y;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         int o[4];
