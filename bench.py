@@ -76,6 +76,9 @@ def load_all(prop, insts, seed0, torch):
         u = W.random_orbitals_torch(seed0 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega, device="cuda")
         prop.load_orbitals(i, u)
         del u
+        if len(insts) > 16 and (i + 1) % 16 == 0:
+            torch.cuda.synchronize()
+            log(f"  loaded {i + 1}/{len(insts)} sub-simulations")
     torch.cuda.synchronize()
 
 

@@ -340,8 +340,10 @@ def random_orbitals_torch(seed: int, n_k: int, n_bands: int, grid, omega: float,
         u = torch.tensordot(u, e2, dims=([3], [0]))             # k b m3 i1 i2
         u = torch.tensordot(u, e3, dims=([2], [0]))             # k b i1 i2 i3
         u = u.permute(0, 1, 4, 3, 2).reshape(nk, n_bands, ng)   # k b (i3 i2 i1)
-        q, r = torch.linalg.qr(u.transpose(1, 2))               # k ng b
-        d = torch.diagonal(r, dim1=1, dim2=2).real.sign()
-        q = q * d[:, None, :]
-        out[k0:k0 + nk] = (q.transpose(1, 2) / (dV ** 0.5)).reshape(nk, n_bands, N3, N2, N1)
+        # Gram-Schmidt in matrix form: with S = u u^H = L L^H (Cholesky), q = L^-1 u has
+        # orthonormal rows and equals the QR factor whose triangle has a positive diagonal
+        s = torch.matmul(u, u.conj().transpose(1, 2).contiguous())
+        l = torch.linalg.cholesky(s)
+        q = torch.linalg.solve_triangular(l, u, upper=False)
+        out[k0:k0 + nk] = (q / (dV ** 0.5)).reshape(nk, n_bands, N3, N2, N1)
     return out
