@@ -96,6 +96,23 @@ __device__ __forceinline__ double wave_total(double v) {
     return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// Wave total of FP32 values with an FP64 result: each row of 16 lanes is summed in
+// FP32 (as the per-lane partials are), the four row sums in FP64.
+__device__ __forceinline__ double wave_total_wide(float v) {
+    v += dpp_f<0xB1, 0xF>(v);
+    v += dpp_f<0x4E, 0xF>(v);
+    v += dpp_f<0x141, 0xF>(v);
+    v += dpp_f<0x140, 0xF>(v);
+    double d = double(v);
+    d += dpp_d<0x142, 0xA>(d);
+    d += dpp_d<0x143, 0xC>(d);
+    const long long b = __builtin_bit_cast(long long, d);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double wave_total_wide(double v) { return wave_total(v); }
+
 // 4th-order central differences (+-2 neighbours)
 #define D1C1 (2.0 / 3.0)
 #define D1C2 (-1.0 / 12.0)
@@ -112,7 +129,7 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, ec, red, jacc, ptp, ptk, ptg, rho, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, ab, wacc, ptp, ptk, ptg, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -128,49 +145,23 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.W = o; o = al16(o + c * ng_max);
     L.cold = o; o = al16(o + 4 * r * nc);
     L.colm = o; o = al16(o + c * nc);
-    L.cole = o; o = al16(o + 16 * nc);
+    L.cole = o; o = al16(o + c * nc);
     L.t2m = o; o = al16(o + c * 3 * nmaxd);
-    L.t2e = o; o = al16(o + 16 * 3 * nmaxd);
+    L.t2e = o; o = al16(o + c * 3 * nmaxd);
     L.apar = o; o = al16(o + 4 * r * na);
     L.part = o; o = al16(o + c * 4 * (ntask_max > 0 ? ntask_max : 1));
-    L.ec = o; o = al16(o + c * 4 * na);
-    L.red = o; o = al16(o + 8 * 8 * (block / 64 + 1));
-    L.jacc = o; o = al16(o + 8 * 4);
+    L.ab = o; o = al16(o + 2 * c * nc);                  // scatter coefficients per column image
+    L.wacc = o; o = al16(o + 8 * 4 * size_t(block / 64));  // FP64 current partial per wave
     // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
     L.ptg = o; o = al16(o + (sl ? r * size_t(nent_max) : 0));
-    L.rho = o; o = al16(o + 8 * size_t(ng_max));  // FP64 density partial of the workgroup
     L.total = o;
     return L;
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
     return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
-}
-
-// Block-wide sum of K <= 8 doubles held by every thread; every thread receives the sums.
-// red must hold (nwaves + 1) * K doubles.
-template <int K>
-__device__ __forceinline__ void block_sum(double *v, double *red, int nwaves) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < K; ++i) v[i] = wave_total(v[i]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) red[wave * K + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x < K) {
-        double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += red[w * K + threadIdx.x];
-        red[nwaves * K + threadIdx.x] = s;  // staging slot after the per-wave area
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < K; ++i) v[i] = red[nwaves * K + i];
-    __syncthreads();
 }
 
 // Uniform real value forced into a scalar register (VALU instructions then read it as
@@ -254,18 +245,16 @@ void k_propagate(PropArgs a) {
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
     C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
-    double2 *cole = reinterpret_cast<double2 *>(smem + L.cole);  // column phase, kappa(t_{n+1})
+    C *cole = reinterpret_cast<C *>(smem + L.cole);         // column phase, kappa(t_{n+1})
     C *t2m = reinterpret_cast<C *>(smem + L.t2m);           // e^{i j2 kappa.a_3/N3}, mid
-    double2 *t2e = reinterpret_cast<double2 *>(smem + L.t2e);
+    C *t2e = reinterpret_cast<C *>(smem + L.t2e);           // same, kappa(t_{n+1})
     Q4 *apar = reinterpret_cast<Q4 *>(smem + L.apar);       // Es dV, Ep dV, Ns, Np per atom
     C *part = reinterpret_cast<C *>(smem + L.part);
-    C *EC = reinterpret_cast<C *>(smem + L.ec);
-    double *red = reinterpret_cast<double *>(smem + L.red);
-    double *jsum = reinterpret_cast<double *>(smem + L.jacc);  // current partial of this workgroup
+    Q4 *AB = reinterpret_cast<Q4 *>(smem + L.ab);           // scatter coefficients A, B per column image
+    double *wacc = reinterpret_cast<double *>(smem + L.wacc);  // current partial per wave (x, y, z, -)
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
     uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
     R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
-    double *RHO = reinterpret_cast<double *>(smem + L.rho);
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
     const auto *gt = gview(gtab<R>(I));
@@ -294,7 +283,7 @@ void k_propagate(PropArgs a) {
     oy[3] = ((i1 >= 2) ? -2 : N1 - 2) * N0;
 
     const double *Am = a.A_tab + 6 * (*a.step_ctr);
-    if (tid < 3) jsum[tid] = 0.0;
+    for (int i = tid; i < 4 * NW; i += BS) wacc[i] = 0.0;
     const double dV = I.dV;
     const int nat = I.nat;
     const int ntask = I.ntask;
@@ -337,7 +326,6 @@ void k_propagate(PropArgs a) {
 #pragma unroll
     for (int z = 0; z < ZL; ++z) {
         vz[z] = active ? vtot[pbase + plane * (z0 + z)] : R(0);
-        if (active) RHO[pbase + plane * (z0 + z)] = 0.0;
     }
 
     // Laplacian coefficients (metric only)
@@ -398,7 +386,9 @@ void k_propagate(PropArgs a) {
             t.x = R(cm);
             t.y = R(sm);
             colm[c] = t;
-            cole[c] = make_double2(ce, se);
+            t.x = R(ce);
+            t.y = R(se);
+            cole[c] = t;
         }
         {
             const double thm = (km[0] * I.hv[2][0] + km[1] * I.hv[2][1] + km[2] * I.hv[2][2]) * inv_pi;
@@ -411,7 +401,9 @@ void k_propagate(PropArgs a) {
                 t.x = R(cm);
                 t.y = R(sm);
                 t2m[j] = t;
-                t2e[j] = make_double2(ce, se);
+                t.x = R(ce);
+                t.y = R(se);
+                t2e[j] = t;
             }
         }
 
@@ -489,20 +481,38 @@ void k_propagate(PropArgs a) {
                     }
                 }
                 __syncthreads();
-                for (int idx = tid; idx < 4 * nat; idx += BS) {
-                    const int at = idx >> 2, l = idx & 3;
-                    C s;
-                    s.x = R(0);
-                    s.y = R(0);
+                // scatter coefficients per column image: on the column the non-local term is
+                //   e^{-i kappa.d} sum_lm f_lm(d) E_l c_lm = g conj(t2(j2)) (A + j2 B),
+                //   A = conj(colphase) (N_s e_s + N_p dcol.e_p),  B = conj(colphase) N_p (a_3/N3).e_p,
+                // with e_lm = E_l dV c_lm and d = dcol + j2 a_3/N3.
+                for (int c = tid; c < ncol; c += BS) {
+                    const Q4 cd = cold[c];
+                    const int at = int(cd.w);
+                    const Q4 ap = apar[at];
+                    C e[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) { e[l].x = R(0); e[l].y = R(0); }
                     for (int t = atom_task[at]; t < atom_task[at + 1]; ++t) {
-                        const C v = part[4 * t + l];
-                        s.x += v.x;
-                        s.y += v.y;
+#pragma unroll
+                        for (int l = 0; l < 4; ++l) {
+                            const C v = part[4 * t + l];
+                            e[l].x += v.x;
+                            e[l].y += v.y;
+                        }
                     }
-                    const R e = (l == 0) ? apar[at].x : apar[at].y;  // E_l dV
-                    s.x *= e;
-                    s.y *= e;
-                    EC[idx] = s;
+                    C k1, k2;
+                    k1.x = ap.z * ap.x * e[0].x + ap.w * ap.y * (cd.x * e[1].x + cd.y * e[2].x + cd.z * e[3].x);
+                    k1.y = ap.z * ap.x * e[0].y + ap.w * ap.y * (cd.x * e[1].y + cd.y * e[2].y + cd.z * e[3].y);
+                    k2.x = ap.w * ap.y * (h2x * e[1].x + h2y * e[2].x + h2z * e[3].x);
+                    k2.y = ap.w * ap.y * (h2x * e[1].y + h2y * e[2].y + h2z * e[3].y);
+                    const C ph = colm[c];
+                    const C A = cmulc(ph, k1), B = cmulc(ph, k2);
+                    Q4 q;
+                    q.x = A.x;
+                    q.y = A.y;
+                    q.z = B.x;
+                    q.w = B.y;
+                    AB[c] = q;
                 }
                 __syncthreads();
                 // ---- 2. h w along the owned column segment
@@ -600,23 +610,17 @@ void k_propagate(PropArgs a) {
                     const int e0s = SL ? int(ptp_l[p]) : pt_ptr[p];
                     const int e1 = SL ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
                     for (int e = e0s; e < e1; ++e) {
-                        int pp, j2u, col;
-                        ent_unpack(SL ? ptk_l[e] : pt_pack[e], pp, j2u, col);
+                        const uint32_t pk = SL ? ptk_l[e] : pt_pack[e];
+                        const int j2u = int((pk >> 13) & 127u), col = int(pk >> 20);
                         const R gv = SL ? ptg_l[e] : pgt[e];
-                        const Q4 cd = cold[col];
-                        const int at = int(cd.w);
-                        const Q4 ap = apar[at];
-                        const C ph = cmul(colm[col], t2m[j2u]);
+                        const Q4 q = AB[col];
+                        const C t2 = t2m[j2u];
                         const R j2 = R(j2u - N2);
-                        const R fs = ap.z * gv, fp = ap.w * gv;
-                        const R dx = cd.x + j2 * h2x, dy = cd.y + j2 * h2y, dz = cd.z + j2 * h2z;
-                        const C *ec = EC + 4 * at;
-                        C sum;
-                        sum.x = fs * ec[0].x + fp * (dx * ec[1].x + dy * ec[2].x + dz * ec[3].x);
-                        sum.y = fs * ec[0].y + fp * (dx * ec[1].y + dy * ec[2].y + dz * ec[3].y);
-                        const C v = cmulc(ph, sum);  // e^{-i kappa.d} * sum
-                        h.x += v.x;
-                        h.y += v.y;
+                        C s;
+                        s.x = (q.x + j2 * q.z) * gv;
+                        s.y = (q.y + j2 * q.w) * gv;
+                        h.x += t2.x * s.x + t2.y * s.y;  // conj(t2) * s
+                        h.y += t2.x * s.y - t2.y * s.x;
                     }
                     hz[z] = h;
                 }
@@ -644,19 +648,25 @@ void k_propagate(PropArgs a) {
             }
             if (a.mode == MODE_APPLY) continue;
 
-            // ---- new orbital: store; FP64 partials of density and current
+            // ---- new orbital: store; FP64 partials of density (into this workgroup's slot,
+            // which only this thread touches at these points) and current
             __syncthreads();
+            const double fo = I.kw[k] * I.occ[b];
             const int ps = opq(pbase + plane * z0);
             if (active) {
+                auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
+                const bool first = (kk == 0) && (bb == 0);
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
                     const int p = ps + plane * z;
                     W[p] = acc[z];
                     if (a.mode == MODE_STEP) gst(ug + p, acc[z]);
+                    const double ux = double(acc[z].x), uy = double(acc[z].y);
+                    const double r = fo * (ux * ux + uy * uy);
+                    rp[p] = first ? r : rp[p] + r;
                 }
             }
             __syncthreads();
-            const double fo = I.kw[k] * I.occ[b];
             // per-thread sums over the owned points in the orbital precision, FP64 beyond
             R qn[4] = {R(0), R(0), R(0), R(0)};  // Q_d = sum Im(conj(u) D1_d u), and sum |u|^2
             const int pk0 = opq(pbase);
@@ -672,8 +682,6 @@ void k_propagate(PropArgs a) {
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
                     const C u = W[p];
-                    const double ux = double(u.x), uy = double(u.y);
-                    RHO[p] += fo * (ux * ux + uy * uy);  // own point: no other thread touches it
                     qn[3] += u.x * u.x + u.y * u.y;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
@@ -725,10 +733,7 @@ void k_propagate(PropArgs a) {
                     ent_unpack(ent_pack[e], p, j2u, col);
                     const R gv = gt[e];
                     const Q4 cd = cold[col];
-                    const double2 phd = cmul(cole[col], t2e[j2u]);
-                    C ph;
-                    ph.x = R(phd.x);
-                    ph.y = R(phd.y);
+                    const C ph = cmul(cole[col], t2e[j2u]);
                     const C x = cmul(ph, W[p]);
                     const R j2 = R(j2u - N2);
                     const R d0 = cd.x + j2 * h2x, d1 = cd.y + j2 * h2y, d2 = cd.z + j2 * h2z;
@@ -748,17 +753,17 @@ void k_propagate(PropArgs a) {
                     qq[5].x += f1 * d2 * x.x; qq[5].y += f1 * d2 * x.y;
                 }
                 double2 tcs, tcp[3], tqq[6];
-                tcs.x = wave_total(double(cs.x));
-                tcs.y = wave_total(double(cs.y));
+                tcs.x = wave_total_wide(cs.x);
+                tcs.y = wave_total_wide(cs.y);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    tcp[i].x = wave_total(double(cp[i].x));
-                    tcp[i].y = wave_total(double(cp[i].y));
+                    tcp[i].x = wave_total_wide(cp[i].x);
+                    tcp[i].y = wave_total_wide(cp[i].y);
                 }
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
-                    tqq[i].x = wave_total(double(qq[i].x));
-                    tqq[i].y = wave_total(double(qq[i].y));
+                    tqq[i].x = wave_total_wide(qq[i].x);
+                    tqq[i].y = wave_total_wide(qq[i].y);
                 }
                 const double Es = par[0], Ep = par[1];
                 const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
@@ -774,36 +779,30 @@ void k_propagate(PropArgs a) {
                     jnl[j] += 2.0 * dV * dV * v;
                 }
             }
-            if (lane != 0) {
-                jnl[0] = jnl[1] = jnl[2] = 0.0;
-            }
-            double v7[7] = {double(qn[0]), double(qn[1]), double(qn[2]), double(qn[3]), jnl[0], jnl[1], jnl[2]};
-            block_sum<7>(v7, red, NW);
-            if (tid == 0) {
-                const double nrm = v7[3] * dV;
+            // wave totals of the kinetic sums; each wave adds its share of this band's
+            // current into its own FP64 slot (a fixed order, no atomics)
+            double qt[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) qt[d] = wave_total_wide(qn[d]);
+            if (lane == 0) {
+                const double nrm = qt[3] * dV;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    const double kin = dV * (I.c[0][q] * v7[0] + I.c[1][q] * v7[1] + I.c[2][q] * v7[2]);
+                    const double kin = dV * (I.c[0][q] * qt[0] + I.c[1][q] * qt[1] + I.c[2][q] * qt[2]);
                     const double keq = kcart[3 * k + q] + Am[3 + q];
-                    jsum[q] += fo * (kin + keq * nrm + v7[4 + q]);
+                    wacc[4 * wave + q] += fo * (kin + keq * nrm + jnl[q]);
                 }
             }
         }
     }
     if (a.mode == MODE_APPLY) return;
-    auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
-    const int pr = opq(pbase + plane * z0);
-    if (active) {
-#pragma unroll
-        for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = RHO[pr + plane * z];
-    }
     __syncthreads();
-    if (tid == 0) {
+    if (tid < 3) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += wacc[4 * w + tid];
         auto *jp = gview_w(I.j_part + 4 * w_slot);
-        jp[0] = jsum[0];
-        jp[1] = jsum[1];
-        jp[2] = jsum[2];
-        jp[3] = 0.0;
+        jp[tid] = s;
+        if (tid == 0) jp[3] = 0.0;
     }
 }
 

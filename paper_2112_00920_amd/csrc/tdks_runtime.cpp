@@ -389,7 +389,9 @@ bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl
         if (N[2] % z) continue;
         int b = N[0] * N[1] * (N[2] / z);
         b = (b + 63) / 64 * 64;
-        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : (fp64 ? 2 : 4));
+        // more than 512 threads need 4 waves per SIMD; otherwise short FP32 segments fit the
+        // 128-register budget of 4 waves, longer ones (and FP64) run at 2
+        int w = (b > 512) ? 4 : (want_w > 0 ? want_w : ((!fp64 && z <= 4) ? 4 : 2));
         if (!propagate_config_ok(b, z, w)) w = (w == 4) ? 2 : 4;
         if (!propagate_config_ok(b, z, w)) continue;
         int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
