@@ -1,6 +1,10 @@
-"""Parity at the full size of the two-step workload (64 sub-simulations x 512 k x
-16 bands on 16^3, FP32 propagation), in the launch configuration the benchmark
-times.  The oracle cannot run the whole workload, so outputs are sampled:
+"""Parity at the full sizes of the batched workloads, in the launch configuration
+the library picks for them (the benchmark's for the two-step workload): the
+two-step workload (64 sub-simulations x 512 k x 16 bands on 16^3), the HHG
+two-step workload (64 x 64 k x 16 bands on 20^3, sin^2 pulse) and the uneven
+batch (40 instances: fcc2 16^3, diamond8 16^3 and 20^3, super16 16x16x32), all
+with FP32 propagation.  The oracle cannot run whole workloads, so outputs are
+sampled:
 
 * density and v_Hxc of one sub-simulation after loading (its full k/band sum),
 * sampled orbitals after one step, propagated by the oracle one by one with the
@@ -74,3 +78,72 @@ def test_two_step_full_size_sampled():
     err = np.max(np.abs(dj[0] - ref))
     _say(f"  current: |dJ_gpu - dJ_oracle(gpu state)| = {err:.2e}, |dJ| = {np.max(np.abs(ref)):.2e}")
     assert err < 1e-12 + 1e-6 * np.max(np.abs(ref))
+
+
+def _sampled_parity(name, sample_ids, n_steps, start, n_orb_k=3, seed0=1000):
+    """Load every instance of a workload, take n_steps from step index `start`, and check
+    sampled instances against the oracle (see the module docstring)."""
+    import paper_2112_00920_amd as tdks
+
+    wl = W.config(name)
+    insts = wl.instances
+    A = wl.field.table(n_steps, wl.dt, start)
+    _say(f"full-size {name} FP32: loading {len(insts)} instances")
+    keep = {}
+    with tdks.Propagator(insts, precision="fp32", dt=wl.dt) as prop:
+        for i, inst in enumerate(insts):
+            u = W.random_orbitals_torch(seed0 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+            prop.load_orbitals(i, u)
+            if i in sample_ids:
+                keep[i] = {"u0": u.cpu().numpy(), "rho0": prop.density(i), "vh0": prop.vhxc(i)}
+            del u
+        _say(f"  tiling {prop.tiling()}; {n_steps} step(s)")
+        prop.step(A)
+        dj = prop.current()
+        for i in sample_ids:
+            keep[i]["u1"] = prop.get_orbitals(i)
+            keep[i]["vh1"] = prop.vhxc(i)
+    rng = np.random.default_rng(5)
+    for i in sample_ids:
+        inst, s = insts[i], keep[i]
+        sysm = System(inst)
+        u32 = s["u0"].astype(np.complex64).astype(np.complex128)
+        rho_o = OP.density(sysm, u32)
+        assert np.max(np.abs(s["rho0"] - rho_o)) / np.max(rho_o) < 1e-12
+        v_o = oracle_vhxc(sysm.cell, rho_o)
+        assert np.max(np.abs(s["vh0"] - v_o)) < 1e-11
+        _say(f"  instance {i} ({inst.cell} {tuple(inst.grid)}, {inst.n_k} k, {inst.n_bands} bands): "
+             "density and v_Hxc after load match")
+        if n_steps == 1:
+            for k in rng.choice(inst.n_k, min(n_orb_k, inst.n_k), replace=False):
+                kap = sysm.k_cart[k] + A[0, 0]
+                ref = OP.taylor_step(sysm, kap, v_o, u32[k], wl.dt)
+                err = np.max(np.abs(s["u1"][k] - ref)) / np.max(np.abs(ref))
+                _say(f"    k {k}: orbital rel err {err:.2e}")
+                assert err < 2e-6
+        # current after the last step, from the GPU state, in FP64 oracle arithmetic
+        J1 = OP.current(sysm, A[-1, 1], s["u1"])
+        J0 = OP.current(sysm, np.zeros(3), u32)
+        ref = J1 - J0
+        err = np.max(np.abs(dj[i][-1] - ref))
+        _say(f"    current: |dJ_gpu - dJ_oracle(gpu state)| = {err:.2e}, |dJ| = {np.max(np.abs(ref)):.2e}")
+        assert err < 1e-12 + 1e-6 * np.max(np.abs(ref))
+        # v_Hxc after the last step follows from the GPU state's density
+        rho1 = OP.density(sysm, s["u1"])
+        assert np.max(np.abs(s["vh1"] - oracle_vhxc(sysm.cell, rho1))) < 1e-11
+
+
+def test_hhg_two_step_full_size_sampled():
+    """64 sub-simulations on 20^3 under the pulse, taken at its peak (A(T/2) = A0)."""
+    wl = W.config("hhg_twostep_g20_mp4_s4")
+    _sampled_parity("hhg_twostep_g20_mp4_s4", [0, 45], 1, int(round(0.5 * wl.field.T / wl.dt)))
+
+
+def test_uneven_batch_full_size_sampled():
+    """The 40-instance uneven batch; one instance of every cell and grid kind is sampled."""
+    wl = W.config("uneven40")
+    first = {}
+    for i, inst in enumerate(wl.instances):
+        first.setdefault((inst.cell, tuple(inst.grid)), i)
+    _say(f"uneven40 kinds: {sorted(first.items())}")
+    _sampled_parity("uneven40", sorted(first.values()), 1, 0.0)
