@@ -18,7 +18,7 @@ struct DevInst {
     int ng;
     int nk, nb, nat;
     int nonorth;        // lattice not orthogonal: mixed second derivatives present
-    int ntask;          // projection tasks (atom-major entry ranges)
+    int ntask;          // projection tasks (chunk ranges of one atom)
     double dV, omega;
     double lat[3][3];   // rows a_d
     double hv[3][3];    // rows a_d / N_d (grid step vectors)
@@ -31,11 +31,13 @@ struct DevInst {
     const double *occ;    // [nb]
     // projectors (k-independent tables, shared between identical cells).  Support
     // points are grouped by "column image" (atom a, unwrapped in-plane grid offsets
-    // j0, j1): d = j0 a_1/N1 + j1 a_2/N2 + j2 a_3/N3 - tau_a.
+    // j0, j1, reference step r along a_3): d = d_ref + (j2 - r) a_3/N3 with
+    // d_ref = j0 a_1/N1 + j1 a_2/N2 + r a_3/N3 - tau_a; r is chosen so that |d_ref|
+    // is small, and tables store the relative step j2 - r.
     int ncol;                  // column images
     const int *col_atom;       // [ncol] atom of each column image
-    const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8
-    const uint32_t *ent_pack;  // atom-major entries: p | (j2 + N3) << 13 | col << 20
+    const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8 | (r + 128) << 16
+    const uint32_t *ent_pack;  // atom-major entries: p | (j2 - r + N3) << 13 | col << 20
     const float *ent_gf;       // radial factor g(|d|) of each entry, FP32 copy
     const double *ent_gd;      // ... FP64 copy
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
@@ -44,7 +46,14 @@ struct DevInst {
     const uint32_t *pt_pack;   // point-major copy of ent_pack
     const float *pt_gf;
     const double *pt_gd;
-    const int2 *task;          // [ntask] {first entry, atom | count << 8}
+    const int *atom_ent;       // [nat+1] first atom-major entry of each atom
+    // chunks: up to 4 consecutive support points of one column image (consecutive j2,
+    // no periodic wrap inside), packed like entries (first point); radial factors
+    // g of the 4 points, zero-padded
+    const uint32_t *chunk_pack;
+    const float *chunk_gf;     // [nchunk][4]
+    const double *chunk_gd;    // [nchunk][4]
+    const int2 *task;          // [ntask] {first chunk, atom | count << 8}
     const int *atom_task;      // [nat+1] first task of each atom
     const double *atom_tau;    // [nat][3] Cartesian positions
     const double *atom_par;    // [nat][4] Es, Ep, Ns, Np
@@ -80,6 +89,7 @@ struct PropArgs {
     int ncol_max;          // most projector column images of an instance in the launch
     int nent_max;          // most projector entries of an instance in the launch
     int nmaxd;             // largest N_d of the launch (phase tables)
+    int plane_max;         // largest N1 N2 of the launch (zeroed slack after the LDS orbital)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
     const void *apply_in;  // MODE_APPLY: input orbitals [nk][nb][ng] complex R of instance

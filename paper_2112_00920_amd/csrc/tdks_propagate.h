@@ -15,9 +15,10 @@
 //        (point-major support list);
 //     3. w <- (-i dt / m) h w, acc += w.
 //   Projector geometry is stored per "column image" (atom a, unwrapped in-plane
-//   offsets j0, j1): d = dcol + j2 a_3/N3 with dcol = j0 a_1/N1 + j1 a_2/N2 - tau_a,
-//   and e^{i kappa.d} = colphase * e^{i j2 kappa.a_3/N3}; both factors are
-//   rebuilt in LDS once per k-point.  After the step the new orbital yields FP64
+//   offsets j0, j1, reference step r along a_3): d = dcol + j2 a_3/N3 with
+//   dcol = j0 a_1/N1 + j1 a_2/N2 + r a_3/N3 - tau_a and j2 counted from r, and
+//   e^{i kappa.d} = colphase * e^{i j2 kappa.a_3/N3}; both factors are rebuilt in
+//   LDS once per k-point.  After the step the new orbital yields FP64
 //   partials of the density (Eq. 3) and of the current (Eqs. 5-6) with
 //   kappa = k + A(t_{n+1}).
 #pragma once
@@ -120,7 +121,8 @@ __device__ __forceinline__ double wave_total_wide(double v) { return wave_total(
 #define D2C1 (4.0 / 3.0)
 #define D2C2 (-1.0 / 12.0)
 
-// packed projector entry: grid index p | (j2 + N3) << 13 | column image << 20
+// packed projector entry: grid index p | (j2 + N3) << 13 | column image << 20 (j2 counted
+// from the column image's reference step)
 __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &col) {
     p = int(v & 8191u);
     j2u = int((v >> 13) & 127u);
@@ -135,19 +137,19 @@ struct PropLds {
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
-                                            int nmaxd, int nat_max, int ntask_max, int block) {
+                                            int nmaxd, int plane_max, int nat_max, int ntask_max, int block) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
     const int nc = ncol_max > 0 ? ncol_max : 1;
     PropLds L;
     size_t o = 0;
-    L.W = o; o = al16(o + c * ng_max);
+    L.W = o; o = al16(o + c * (ng_max + 3 * size_t(plane_max)));  // + zeroed slack read by padded chunks
     L.cold = o; o = al16(o + 4 * r * nc);
     L.colm = o; o = al16(o + c * nc);
     L.cole = o; o = al16(o + c * nc);
-    L.t2m = o; o = al16(o + c * 3 * nmaxd);
-    L.t2e = o; o = al16(o + c * 3 * nmaxd);
+    L.t2m = o; o = al16(o + c * (3 * nmaxd + 3));
+    L.t2e = o; o = al16(o + c * (3 * nmaxd + 3));
     L.apar = o; o = al16(o + 4 * r * na);
     L.part = o; o = al16(o + c * 4 * (ntask_max > 0 ? ntask_max : 1));
     L.ab = o; o = al16(o + 2 * c * nc);                  // scatter coefficients per column image
@@ -161,7 +163,8 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
-    return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max, block).total;
+    return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max, a.nat_max, a.ntask_max,
+                    block).total;
 }
 
 // Uniform real value forced into a scalar register (VALU instructions then read it as
@@ -210,14 +213,30 @@ template <typename T> __device__ __forceinline__ void gst(T *p, T x) {
     *(TDKS_GLOBAL typename NV2<T>::type *)p = v;
 }
 
+// four-component global load (chunk radial factors)
+template <typename Q> struct NV4;
+template <> struct NV4<float4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct NV4<double4> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename Q> __device__ __forceinline__ Q gld4(const Q *p) {
+    const auto v = *(const TDKS_GLOBAL typename NV4<Q>::type *)p;
+    Q r;
+    r.x = v.x;
+    r.y = v.y;
+    r.z = v.z;
+    r.w = v.w;
+    return r;
+}
+
 template <typename R> __device__ __forceinline__ const R *gtab(const DevInst &I);
 template <> __device__ __forceinline__ const float *gtab<float>(const DevInst &I) { return I.ent_gf; }
 template <> __device__ __forceinline__ const double *gtab<double>(const DevInst &I) { return I.ent_gd; }
+template <typename R> __device__ __forceinline__ const R *chunktab(const DevInst &I);
+template <> __device__ __forceinline__ const float *chunktab<float>(const DevInst &I) { return I.chunk_gf; }
+template <> __device__ __forceinline__ const double *chunktab<double>(const DevInst &I) { return I.chunk_gd; }
 template <typename R> __device__ __forceinline__ const R *ptgtab(const DevInst &I);
 template <> __device__ __forceinline__ const float *ptgtab<float>(const DevInst &I) { return I.pt_gf; }
 template <> __device__ __forceinline__ const double *ptgtab<double>(const DevInst &I) { return I.pt_gd; }
 
-constexpr int kBatch = 4;  // projector entries a lane loads before using them
 
 template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
@@ -240,8 +259,8 @@ void k_propagate(PropArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = BS >> 6;
 
-    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max,
-                               a.ntask_max, BS);
+    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max,
+                               a.nat_max, a.ntask_max, BS);
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
     C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
@@ -260,6 +279,8 @@ void k_propagate(PropArgs a) {
     const auto *gt = gview(gtab<R>(I));
     const auto *pgt = gview(ptgtab<R>(I));
     const auto *ent_pack = gview(I.ent_pack);
+    const auto *chunk_pack = gview(I.chunk_pack);
+    const Q4 *chunk_g = reinterpret_cast<const Q4 *>(chunktab<R>(I));
     const auto *pt_ptr = gview(I.pt_ptr);
     const auto *pt_pack = gview(I.pt_pack);
     const int2 *task = I.task;
@@ -284,6 +305,12 @@ void k_propagate(PropArgs a) {
 
     const double *Am = a.A_tab + 6 * (*a.step_ctr);
     for (int i = tid; i < 4 * NW; i += BS) wacc[i] = 0.0;
+    for (int i = tid; i < 3 * N0 * N1; i += BS) {  // slack after the orbital, read (times g = 0) by padded chunks
+        C zero;
+        zero.x = R(0);
+        zero.y = R(0);
+        W[ng + i] = zero;
+    }
     const double dV = I.dV;
     const int nat = I.nat;
     const int ntask = I.ntask;
@@ -294,12 +321,13 @@ void k_propagate(PropArgs a) {
     for (int c = tid; c < ncol; c += BS) {
         const int at = I.col_atom[c];
         const int j01 = I.col_j01[c];
-        const double j0 = double((j01 & 255) - N0), j1 = double((j01 >> 8) - N1);
+        const double j0 = double((j01 & 255) - N0), j1 = double(((j01 >> 8) & 255) - N1);
+        const double jr = double(((j01 >> 16) & 255) - 128);
         const double *tau = I.atom_tau + 3 * at;
         Q4 q;
-        q.x = R(j0 * I.hv[0][0] + j1 * I.hv[1][0] - tau[0]);
-        q.y = R(j0 * I.hv[0][1] + j1 * I.hv[1][1] - tau[1]);
-        q.z = R(j0 * I.hv[0][2] + j1 * I.hv[1][2] - tau[2]);
+        q.x = R(j0 * I.hv[0][0] + j1 * I.hv[1][0] + jr * I.hv[2][0] - tau[0]);
+        q.y = R(j0 * I.hv[0][1] + j1 * I.hv[1][1] + jr * I.hv[2][1] - tau[1]);
+        q.z = R(j0 * I.hv[0][2] + j1 * I.hv[1][2] + jr * I.hv[2][2] - tau[2]);
         q.w = R(at);
         cold[c] = q;
     }
@@ -374,11 +402,12 @@ void k_propagate(PropArgs a) {
         for (int c = tid; c < ncol; c += BS) {
             const int at = I.col_atom[c];
             const int j01 = I.col_j01[c];
-            const double j0 = double((j01 & 255) - N0), j1 = double((j01 >> 8) - N1);
+            const double j0 = double((j01 & 255) - N0), j1 = double(((j01 >> 8) & 255) - N1);
+            const double jr = double(((j01 >> 16) & 255) - 128);
             const double *tau = I.atom_tau + 3 * at;
-            double dcx = j0 * I.hv[0][0] + j1 * I.hv[1][0] - tau[0];
-            double dcy = j0 * I.hv[0][1] + j1 * I.hv[1][1] - tau[1];
-            double dcz = j0 * I.hv[0][2] + j1 * I.hv[1][2] - tau[2];
+            double dcx = j0 * I.hv[0][0] + j1 * I.hv[1][0] + jr * I.hv[2][0] - tau[0];
+            double dcy = j0 * I.hv[0][1] + j1 * I.hv[1][1] + jr * I.hv[2][1] - tau[1];
+            double dcz = j0 * I.hv[0][2] + j1 * I.hv[1][2] + jr * I.hv[2][2] - tau[2];
             double sm, cm, se, ce;
             sincospi((km[0] * dcx + km[1] * dcy + km[2] * dcz) * inv_pi, &sm, &cm);
             sincospi((ke[0] * dcx + ke[1] * dcy + ke[2] * dcz) * inv_pi, &se, &ce);
@@ -393,7 +422,7 @@ void k_propagate(PropArgs a) {
         {
             const double thm = (km[0] * I.hv[2][0] + km[1] * I.hv[2][1] + km[2] * I.hv[2][2]) * inv_pi;
             const double the = (ke[0] * I.hv[2][0] + ke[1] * I.hv[2][1] + ke[2] * I.hv[2][2]) * inv_pi;
-            for (int j = tid; j < 3 * N2; j += BS) {
+            for (int j = tid; j < 3 * N2 + 3; j += BS) {
                 double sm, cm, se, ce;
                 sincospi(double(j - N2) * thm, &sm, &cm);
                 sincospi(double(j - N2) * the, &se, &ce);
@@ -433,42 +462,48 @@ void k_propagate(PropArgs a) {
 #pragma unroll 1
             for (int m = 1; m <= norder; ++m) {
                 __syncthreads();  // W holds w_{m-1}
-                // ---- 1. projections c = <P|w> (atom-major tasks, one wave each)
+                // ---- 1. projections c = <P|w> (tasks of chunks of one atom, one wave each).
+                // On a chunk (points j2_0 + i, i < 4, of one column image) with x_i = t2(j2_i) w_i g_i:
+                //   sum g d e^{i kappa.d} w = colphase (d_0 X0 + (a_3/N3) X1),
+                //   d_0 = dcol + j2_0 a_3/N3 (the first point's offset), X0 = sum x_i, X1 = sum i x_i.
                 for (int t = wave; t < ntask; t += NW) {
                     const int2 tk = gld(task + t);
-                    const int e0 = tk.x, cnt = tk.y >> 8, at = tk.y & 255;
-                    const Q4 ap = apar[at];
+                    const int c0 = tk.x, cnt = tk.y >> 8, at = tk.y & 255;
                     C s[4];
 #pragma unroll
                     for (int l = 0; l < 4; ++l) { s[l].x = R(0); s[l].y = R(0); }
-                    for (int base = lane; base < cnt; base += 64 * kBatch) {
-                        uint32_t pk[kBatch];
-                        R gv[kBatch];
+                    for (int ci = lane; ci < cnt; ci += 64) {
+                        const uint32_t cp = chunk_pack[c0 + ci];
+                        const Q4 g4 = gld4(chunk_g + c0 + ci);
+                        const int p0 = int(cp & 8191u), j2u0 = int((cp >> 13) & 127u), col = int(cp >> 20);
+                        const R gg[4] = {g4.x, g4.y, g4.z, g4.w};
+                        C y0, y1;
+                        y0.x = R(0); y0.y = R(0); y1.x = R(0); y1.y = R(0);
 #pragma unroll
-                        for (int q = 0; q < kBatch; ++q) {
-                            const int i = base + 64 * q;
-                            pk[q] = (i < cnt) ? ent_pack[e0 + i] : 0u;
-                            gv[q] = (i < cnt) ? gt[e0 + i] : R(0);
+                        for (int i = 0; i < 4; ++i) {
+                            C x = cmul(t2m[j2u0 + i], W[p0 + plane * i]);
+                            x.x *= gg[i];
+                            x.y *= gg[i];
+                            y0.x += x.x;
+                            y0.y += x.y;
+                            if (i > 0) {
+                                y1.x += R(i) * x.x;
+                                y1.y += R(i) * x.y;
+                            }
                         }
-#pragma unroll
-                        for (int q = 0; q < kBatch; ++q) {
-                            int p, j2u, col;
-                            ent_unpack(pk[q], p, j2u, col);
-                            const Q4 cd = cold[col];
-                            const C ph = cmul(colm[col], t2m[j2u]);
-                            const C x = cmul(ph, W[p]);
-                            const R j2 = R(j2u - N2);
-                            const R fs = ap.z * gv[q], fp = ap.w * gv[q];
-                            const R dx = cd.x + j2 * h2x, dy = cd.y + j2 * h2y, dz = cd.z + j2 * h2z;
-                            s[0].x += fs * x.x;
-                            s[0].y += fs * x.y;
-                            s[1].x += fp * dx * x.x;
-                            s[1].y += fp * dx * x.y;
-                            s[2].x += fp * dy * x.x;
-                            s[2].y += fp * dy * x.y;
-                            s[3].x += fp * dz * x.x;
-                            s[3].y += fp * dz * x.y;
-                        }
+                        const C ph = colm[col];
+                        const Q4 cd = cold[col];
+                        const C X0 = cmul(ph, y0), X1 = cmul(ph, y1);
+                        const R j20 = R(j2u0 - N2);
+                        const R d0x = cd.x + j20 * h2x, d0y = cd.y + j20 * h2y, d0z = cd.z + j20 * h2z;
+                        s[0].x += X0.x;
+                        s[0].y += X0.y;
+                        s[1].x += d0x * X0.x + h2x * X1.x;
+                        s[1].y += d0x * X0.y + h2x * X1.y;
+                        s[2].x += d0y * X0.x + h2y * X1.x;
+                        s[2].y += d0y * X0.y + h2y * X1.y;
+                        s[3].x += d0z * X0.x + h2z * X1.x;
+                        s[3].y += d0z * X0.y + h2z * X1.y;
                     }
 #pragma unroll
                     for (int l = 0; l < 4; ++l) {
@@ -476,8 +511,15 @@ void k_propagate(PropArgs a) {
                         s[l].y = wave_total(s[l].y);
                     }
                     if (lane == 0) {
+                        const Q4 ap = apar[at];  // N_s, N_p in .z, .w
 #pragma unroll
-                        for (int l = 0; l < 4; ++l) part[4 * t + l] = s[l];
+                        for (int l = 0; l < 4; ++l) {
+                            const R f = (l == 0) ? ap.z : ap.w;
+                            C v;
+                            v.x = f * s[l].x;
+                            v.y = f * s[l].y;
+                            part[4 * t + l] = v;
+                        }
                     }
                 }
                 __syncthreads();
@@ -713,9 +755,7 @@ void k_propagate(PropArgs a) {
             double jnl[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
             for (int at = wave; at < nat; at += NW) {
-                const int e_beg = gld(task + atom_task[at]).x;
-                const int tl = atom_task[at + 1] - 1;
-                const int e_end = gld(task + tl).x + (gld(task + tl).y >> 8);
+                const int e_beg = I.atom_ent[at], e_end = I.atom_ent[at + 1];
                 const double *par = I.atom_par + 4 * at;
                 const double ns = par[2], np = par[3];
                 // per-lane moment sums in the orbital precision (products of orbital values),

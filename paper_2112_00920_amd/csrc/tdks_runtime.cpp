@@ -50,6 +50,10 @@ struct TableSet {
     std::vector<double> ent_g, pt_g;
     std::vector<float> ent_gf, pt_gf;
     std::vector<int> pt_ptr, atom_task, atom_ent;  // atom_ent: [nat+1] first entry of each atom
+    std::vector<uint32_t> chunk_pack;
+    std::vector<double> chunk_g;   // [nchunk][4]
+    std::vector<float> chunk_gf;
+    std::vector<int> atom_chunk;   // [nat+1] first chunk of each atom
     std::vector<uint16_t> pt_ptr16;
     std::vector<int2> task;
     std::vector<double> atom_tau, atom_par;
@@ -60,8 +64,11 @@ struct TableSet {
     uint32_t *d_ent_pack = nullptr, *d_pt_pack = nullptr;
     double *d_ent_g = nullptr, *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
     float *d_ent_gf = nullptr, *d_pt_gf = nullptr;
-    int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
+    int *d_pt_ptr = nullptr, *d_atom_task = nullptr, *d_atom_ent = nullptr;
     uint16_t *d_pt_ptr16 = nullptr;
+    uint32_t *d_chunk_pack = nullptr;
+    double *d_chunk_g = nullptr;
+    float *d_chunk_gf = nullptr;
     int2 *d_task = nullptr;
 };
 
@@ -89,7 +96,7 @@ struct ShapeClass {
     bool nonorth;
     int zl = 0, block = 0, minw = 0, sl = 0;
     int wbeg = 0, wend = 0;
-    int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
+    int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0, plane_max = 0;
 };
 
 }  // namespace
@@ -259,6 +266,9 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     T.col_atom.clear();
     T.col_j01.clear();
     T.atom_ent.assign(nat + 1, 0);
+    T.chunk_pack.clear();
+    T.chunk_g.clear();
+    T.atom_chunk.clear();
     for (int a = 0; a < nat; ++a) {
         T.atom_ent[a] = int(ents.size());
         const tdks_species &sp = d.species[d.atom_species[a]];
@@ -289,16 +299,75 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                     }
                 }
         if (bycol.empty()) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
+        // reference step r of each column image: the a_3 offset that brings its points
+        // closest to the atom (d_ref = dcol + r a_3/N3); entries store j2 - r, so that
+        // every offset the kernels form from tables stays small
+        std::map<int, int> colref;
+        {
+            const double *h2 = I.hv[2];
+            const double hh = h2[0] * h2[0] + h2[1] * h2[1] + h2[2] * h2[2];
+            for (auto &kv : bycol) {
+                const double j0 = double((kv.first & 255) - I.N[0]), j1 = double((kv.first >> 8) - I.N[1]);
+                double dd = 0.0;
+                for (int q = 0; q < 3; ++q)
+                    dd += (j0 * I.hv[0][q] + j1 * I.hv[1][q] - T.atom_tau[3 * a + q]) * h2[q];
+                const int r = int(std::lround(-dd / hh));
+                if (r < -127 || r > 127) return fail(TDKS_E_UNSUPPORTED, "atom %d: column reference out of range", a);
+                colref[kv.first] = r;
+                for (auto &e : kv.second) {
+                    const int f = e.first - r;  // (j2 - r) + N3 with j2 = u2 - N3
+                    if (f < 0 || f >= 2 * I.N[2])
+                        return fail(TDKS_E_ARG, "atom %d: projector support spans more than the cell along a_3", a);
+                }
+            }
+        }
+        // chunks of this atom: runs of up to 4 consecutive j2 on one column image, cut where
+        // the grid index wraps; ordered by (first j2, j1, j0) so that the lanes of a wave
+        // start on neighbouring grid points
+        T.atom_chunk.push_back(int(T.chunk_pack.size()));
+        {
+            struct Ch { long long key; uint32_t pack; double g[4]; };
+            std::vector<Ch> chs;
+            int col = int(T.col_atom.size());
+            for (auto &kv : bycol) {
+                auto pts = kv.second;
+                std::sort(pts.begin(), pts.end(), [](const std::pair<int, std::pair<int, double>> &x,
+                                                     const std::pair<int, std::pair<int, double>> &y) {
+                    return x.first < y.first;
+                });
+                size_t i = 0;
+                while (i < pts.size()) {
+                    Ch c{};
+                    const int u2 = pts[i].first, p = pts[i].second.first;
+                    c.key = (static_cast<long long>(u2) << 16) | ((kv.first >> 8) << 8) | (kv.first & 255);
+                    c.pack = uint32_t(p) | (uint32_t(u2 - colref[kv.first]) << 13) | (uint32_t(col) << 20);
+                    int n = 0;
+                    while (n < 4 && i < pts.size() && pts[i].first == u2 + n &&
+                           (n == 0 || pts[i].second.first == p + n * I.N[0] * I.N[1])) {
+                        c.g[n] = pts[i].second.second;
+                        ++n;
+                        ++i;
+                    }
+                    chs.push_back(c);
+                }
+                ++col;
+            }
+            std::sort(chs.begin(), chs.end(), [](const Ch &x, const Ch &y) { return x.key < y.key; });
+            for (const Ch &c : chs) {
+                T.chunk_pack.push_back(c.pack);
+                for (int q = 0; q < 4; ++q) T.chunk_g.push_back(c.g[q]);
+            }
+        }
         // entries of one atom in plane-major order (j2, then j1, j0): lanes that walk
         // consecutive entries read consecutive grid points, i.e. distinct LDS banks
         std::vector<std::pair<long long, Ent>> order;
         for (auto &kv : bycol) {
             const int col = int(T.col_atom.size());
             T.col_atom.push_back(a);
-            T.col_j01.push_back(kv.first);
+            T.col_j01.push_back(kv.first | ((colref[kv.first] + 128) << 16));
             for (auto &e : kv.second) {
                 const long long key = (static_cast<long long>(e.first) << 16) | ((kv.first >> 8) << 8) | (kv.first & 255);
-                order.push_back({key, Ent{col, e.first, e.second.first, e.second.second}});
+                order.push_back({key, Ent{col, e.first - colref[kv.first], e.second.first, e.second.second}});
             }
         }
         std::sort(order.begin(), order.end(), [](const std::pair<long long, Ent> &x,
@@ -306,6 +375,8 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         for (auto &o : order) ents.push_back(o.second);
     }
     T.atom_ent[nat] = int(ents.size());
+    T.atom_chunk.push_back(int(T.chunk_pack.size()));
+    T.chunk_gf.assign(T.chunk_g.begin(), T.chunk_g.end());
     if (T.col_atom.size() >= 4096)
         return fail(TDKS_E_UNSUPPORTED, "%zu projector column images exceed 4095", T.col_atom.size());
     std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
@@ -335,16 +406,16 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     return TDKS_OK;
 }
 
-// projection tasks: contiguous entry ranges of one atom, sized so that the block's waves
+// projection tasks: contiguous chunk ranges of one atom, sized so that the block's waves
 // get about one task each (one wave reduction per task)
 void build_tasks(TableSet &T, int block) {
     const int nwaves = std::max(1, block / 64);
-    const long long total = std::max(1, T.atom_ent[T.nat]);
+    const long long total = std::max(1, T.atom_chunk[T.nat]);
     T.task.clear();
     T.atom_task.assign(T.nat + 1, 0);
     for (int a = 0; a < T.nat; ++a) {
         T.atom_task[a] = int(T.task.size());
-        const int b0 = T.atom_ent[a], cnt = T.atom_ent[a + 1] - b0;
+        const int b0 = T.atom_chunk[a], cnt = T.atom_chunk[a + 1] - b0;
         const int nt = std::max(1, int((nwaves * (long long)cnt + total / 2) / total));
         const int len = (cnt + nt - 1) / nt;
         for (int s = 0; s < cnt; s += len) T.task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
@@ -434,6 +505,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.ncol_max = S.ncol_max;
     a.nent_max = S.nent_max;
     a.nmaxd = S.nmaxd;
+    a.plane_max = S.plane_max;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
     a.apply_in = nullptr;
@@ -662,6 +734,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         S.ncol_max = std::max(S.ncol_max, int(T.col_atom.size()));
         S.nent_max = std::max(S.nent_max, int(T.ent_pack.size()));
         S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
+        S.plane_max = std::max(S.plane_max, I.N[0] * I.N[1]);
         S.nat_max = std::max(S.nat_max, T.nat);
         S.ntask_max = std::max(S.ntask_max, int(T.task.size()));
     }
@@ -722,6 +795,10 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         CHK(upload(c, &T.d_pt_gf, T.pt_gf));
         CHK(upload(c, &T.d_task, T.task));
         CHK(upload(c, &T.d_atom_task, T.atom_task));
+        CHK(upload(c, &T.d_atom_ent, T.atom_ent));
+        CHK(upload(c, &T.d_chunk_pack, T.chunk_pack));
+        CHK(upload(c, &T.d_chunk_g, T.chunk_g));
+        CHK(upload(c, &T.d_chunk_gf, T.chunk_gf));
         CHK(upload(c, &T.d_atom_tau, T.atom_tau));
         CHK(upload(c, &T.d_atom_par, T.atom_par));
     }
@@ -794,6 +871,10 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.pt_gd = T.d_pt_g;
         D.task = T.d_task;
         D.atom_task = T.d_atom_task;
+        D.atom_ent = T.d_atom_ent;
+        D.chunk_pack = T.d_chunk_pack;
+        D.chunk_gf = T.d_chunk_gf;
+        D.chunk_gd = T.d_chunk_g;
         D.atom_tau = T.d_atom_tau;
         D.atom_par = T.d_atom_par;
         D.rho_part = I.d_rho_part;
