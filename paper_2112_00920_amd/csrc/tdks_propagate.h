@@ -606,13 +606,16 @@ void k_propagate(PropArgs a) {
                         } else {
                             p1 = zn[0]; m1 = zn[1]; p2 = zn[2]; m2 = zn[3];
                         }
-                        h.x += a1[d] * (p1.x + m1.x) + a2[d] * (p2.x + m2.x);
-                        h.y += a1[d] * (p1.y + m1.y) + a2[d] * (p2.y + m2.y);
-                        // -i (b1 (p1 - m1) + b2 (p2 - m2))
-                        const R qx = b1[d] * (p1.x - m1.x) + b2[d] * (p2.x - m2.x);
-                        const R qy = b1[d] * (p1.y - m1.y) + b2[d] * (p2.y - m2.y);
-                        h.x += qy;
-                        h.y -= qx;
+                        // a1 (p1 + m1) + a2 (p2 + m2) - i (b1 (p1 - m1) + b2 (p2 - m2)), one
+                        // multiply-add per neighbour pair and component
+                        h.x = fma(a1[d], p1.x + m1.x, h.x);
+                        h.x = fma(a2[d], p2.x + m2.x, h.x);
+                        h.x = fma(b1[d], p1.y - m1.y, h.x);
+                        h.x = fma(b2[d], p2.y - m2.y, h.x);
+                        h.y = fma(a1[d], p1.y + m1.y, h.y);
+                        h.y = fma(a2[d], p2.y + m2.y, h.y);
+                        h.y = fma(-b1[d], p1.x - m1.x, h.y);
+                        h.y = fma(-b2[d], p2.x - m2.x, h.y);
                     }
                     if (NONORTH) {
                         // - sum_{d<e} g_de D1_d D1_e w, all from LDS
@@ -709,15 +712,14 @@ void k_propagate(PropArgs a) {
                 }
             }
             __syncthreads();
-            // per-thread sums over the owned points in the orbital precision, FP64 beyond
-            R qn[4] = {R(0), R(0), R(0), R(0)};  // Q_d = sum Im(conj(u) D1_d u), and sum |u|^2
+            // per-thread sums over the owned points in the orbital precision, FP64 beyond.
+            // Summed over the whole periodic grid, sum_p Im(conj(u_p) (u_{p+s} - u_{p-s}))
+            // = 2 sum_p Im(conj(u_p) u_{p+s}), so only forward neighbours are needed:
+            // Q_d = sum Im(conj(u) D1_d u) = 2 (D1C1 q1_d + D1C2 q2_d).
+            R q1[3] = {R(0), R(0), R(0)}, q2[3] = {R(0), R(0), R(0)};
+            R qn[4] = {R(0), R(0), R(0), R(0)};
             const int pk0 = opq(pbase);
-            int oxk[4], oyk[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                oxk[s] = opq(ox[s]);
-                oyk[s] = opq(oy[s]);
-            }
+            const int oxk1 = opq(ox[0]), oxk2 = opq(ox[2]), oyk1 = opq(oy[0]), oyk2 = opq(oy[2]);
             if (active) {
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
@@ -727,28 +729,30 @@ void k_propagate(PropArgs a) {
                     qn[3] += u.x * u.x + u.y * u.y;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        int o[4];
+                        C u1, u2;
                         if (d == 0) {
-                            o[0] = oxk[0]; o[1] = oxk[1]; o[2] = oxk[2]; o[3] = oxk[3];
+                            u1 = W[p + oxk1];
+                            u2 = W[p + oxk2];
                         } else if (d == 1) {
-                            o[0] = oyk[0]; o[1] = oyk[1]; o[2] = oyk[2]; o[3] = oyk[3];
+                            u1 = W[p + oyk1];
+                            u2 = W[p + oyk2];
                         } else {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                const int dz = (s == 0) ? 1 : (s == 1) ? -1 : (s == 2) ? 2 : -2;
-                                int zw = zg + dz;
-                                zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
-                                o[s] = plane * (zw - zg);
+                            for (int s = 1; s <= 2; ++s) {
+                                const int zw = (zg + s >= N2) ? zg + s - N2 : zg + s;
+                                const C v = W[pk0 + plane * zw];
+                                if (s == 1) u1 = v; else u2 = v;
                             }
                         }
-                        const C p1 = W[p + o[0]], m1 = W[p + o[1]];
-                        const C p2 = W[p + o[2]], m2 = W[p + o[3]];
-                        const R dx = R(D1C1) * (p1.x - m1.x) + R(D1C2) * (p2.x - m2.x);
-                        const R dy = R(D1C1) * (p1.y - m1.y) + R(D1C2) * (p2.y - m2.y);
-                        qn[d] += u.x * dy - u.y * dx;
+                        q1[d] = fma(u.x, u1.y, q1[d]);
+                        q1[d] = fma(-u.y, u1.x, q1[d]);
+                        q2[d] = fma(u.x, u2.y, q2[d]);
+                        q2[d] = fma(-u.y, u2.x, q2[d]);
                     }
                 }
             }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) qn[d] = R(2) * (R(D1C1) * q1[d] + R(D1C2) * q2[d]);
             // non-local current: one wave per atom.  With c = <P|u>, c_d = <d P|u> the
             // commutator term is sum_lm 2 E_l Im(conj(c_d,lm) c_lm); since
             // d_j f_s = (N_s/N_p) f_p,j, only c_s, c_p,i and Q_ij = <d_j P_p,i|u> are needed.
