@@ -90,6 +90,7 @@ struct PropArgs {
     int nent_max;          // most projector entries of an instance in the launch
     int nmaxd;             // largest N_d of the launch (phase tables)
     int plane_max;         // largest N1 N2 of the launch (zeroed slack after the LDS orbital)
+    int rho_lds;           // accumulate the FP64 density partial in LDS (else in the global slot)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
     const void *apply_in;  // MODE_APPLY: input orbitals [nk][nb][ng] complex R of instance

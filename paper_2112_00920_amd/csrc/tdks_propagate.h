@@ -131,13 +131,14 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, ab, wacc, ptp, ptk, ptg, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, ab, wacc, ptp, ptk, ptg, rho, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
-                                            int nmaxd, int plane_max, int nat_max, int ntask_max, int block) {
+                                            int nmaxd, int plane_max, int nat_max, int ntask_max, int block,
+                                            int rho_lds) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
@@ -158,13 +159,14 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
     L.ptg = o; o = al16(o + (sl ? r * size_t(nent_max) : 0));
+    L.rho = o; o = al16(o + (rho_lds ? 8 * size_t(ng_max) : 0));  // FP64 density partial
     L.total = o;
     return L;
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
     return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max, a.nat_max, a.ntask_max,
-                    block).total;
+                    block, a.rho_lds).total;
 }
 
 // Uniform real value forced into a scalar register (VALU instructions then read it as
@@ -260,7 +262,7 @@ void k_propagate(PropArgs a) {
     const int NW = BS >> 6;
 
     const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max,
-                               a.nat_max, a.ntask_max, BS);
+                               a.nat_max, a.ntask_max, BS, a.rho_lds);
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
     C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
@@ -274,6 +276,8 @@ void k_propagate(PropArgs a) {
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
     uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
     R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
+    double *RHO = reinterpret_cast<double *>(smem + L.rho);
+    const bool rho_lds = sizeof(R) == 4 && a.rho_lds != 0;  // the FP64 kernels keep it in HBM
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
     const auto *gt = gview(gtab<R>(I));
@@ -693,8 +697,8 @@ void k_propagate(PropArgs a) {
             }
             if (a.mode == MODE_APPLY) continue;
 
-            // ---- new orbital: store; FP64 partials of density (into this workgroup's slot,
-            // which only this thread touches at these points) and current
+            // ---- new orbital: store; FP64 partials of density (in LDS or in this work item's
+            // global slot; only this thread touches these points) and current
             __syncthreads();
             const double fo = I.kw[k] * I.occ[b];
             const int ps = opq(pbase + plane * z0);
@@ -708,7 +712,10 @@ void k_propagate(PropArgs a) {
                     if (a.mode == MODE_STEP) gst(ug + p, acc[z]);
                     const double ux = double(acc[z].x), uy = double(acc[z].y);
                     const double r = fo * (ux * ux + uy * uy);
-                    rp[p] = first ? r : rp[p] + r;
+                    if (rho_lds)
+                        RHO[p] = first ? r : RHO[p] + r;
+                    else
+                        rp[p] = first ? r : rp[p] + r;
                 }
             }
             __syncthreads();
@@ -840,6 +847,12 @@ void k_propagate(PropArgs a) {
         }
     }
     if (a.mode == MODE_APPLY) return;
+    if (rho_lds && active) {
+        auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
+        const int pr = opq(pbase + plane * z0);
+#pragma unroll
+        for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = RHO[pr + plane * z];
+    }
     __syncthreads();
     if (tid < 3) {
         double s = 0.0;

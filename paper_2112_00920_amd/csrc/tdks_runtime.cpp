@@ -94,7 +94,7 @@ struct InstHost {
 struct ShapeClass {
     int N[3];
     bool nonorth;
-    int zl = 0, block = 0, minw = 0, sl = 0;
+    int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0;
     int wbeg = 0, wend = 0;
     int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0, plane_max = 0;
 };
@@ -506,6 +506,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.nent_max = S.nent_max;
     a.nmaxd = S.nmaxd;
     a.plane_max = S.plane_max;
+    a.rho_lds = S.rho_lds;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
     a.apply_in = nullptr;
@@ -740,8 +741,13 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     }
     for (ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
-        // FP32: stage the point-major projector tables in LDS when they fit
+        // FP32: stage the point-major projector tables in LDS when they fit; then keep the
+        // density partial in LDS too if there is room (in the global slot, every band's
+        // update of it would leave L2)
         S.sl = (!c->fp64 && propagate_lds_bytes(c->fp64, 1, a, S.block) <= 160 * 1024) ? 1 : 0;
+        a.rho_lds = 1;
+        S.rho_lds = (!c->fp64 && propagate_lds_bytes(c->fp64, S.sl, a, S.block) <= 160 * 1024) ? 1 : 0;
+        a.rho_lds = S.rho_lds;
         const size_t lds = propagate_lds_bytes(c->fp64, S.sl, a, S.block);
         if (lds > 160 * 1024)
             return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of LDS per workgroup", S.N[0], S.N[1],
