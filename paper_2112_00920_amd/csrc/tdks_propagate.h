@@ -114,6 +114,69 @@ __device__ __forceinline__ double wave_total_wide(float v) {
 }
 __device__ __forceinline__ double wave_total_wide(double v) { return wave_total(v); }
 
+// Wave totals of four values at once.  v_permlane32_swap exchanges rows 2-3 of its first
+// operand with rows 0-1 of its second and v_permlane16_swap the odd rows of the first with
+// the even rows of the second (rows of 16 lanes), so adding a swapped pair folds the rows
+// of two values into one register.  Two folds leave v0..v3 in rows 0..3 of one register,
+// each summed lane by lane over the four rows; DPP then sums each row, and every lane of
+// row r holds the total of v_r.
+__device__ __forceinline__ unsigned fbits(float x) { return __builtin_bit_cast(unsigned, x); }
+__device__ __forceinline__ float bitsf(unsigned x) { return __builtin_bit_cast(float, x); }
+__device__ __forceinline__ float fold32(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane32_swap(fbits(x), fbits(y), false, false);
+    return bitsf(r[0]) + bitsf(r[1]);  // rows: x r0+r2, x r1+r3, y r0+r2, y r1+r3
+}
+__device__ __forceinline__ float fold16(float x, float y) {
+    const auto r = __builtin_amdgcn_permlane16_swap(fbits(x), fbits(y), false, false);
+    return bitsf(r[0]) + bitsf(r[1]);  // rows: x r0+r1, y r0+r1, x r2+r3, y r2+r3
+}
+__device__ __forceinline__ double fold32(double x, double y) {
+    const long long bx = __builtin_bit_cast(long long, x), by = __builtin_bit_cast(long long, y);
+    const auto lo = __builtin_amdgcn_permlane32_swap(unsigned(bx), unsigned(by), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(unsigned(bx >> 32), unsigned(by >> 32), false, false);
+    const double x2 = __builtin_bit_cast(double, (static_cast<long long>(hi[0]) << 32) | lo[0]);
+    const double y2 = __builtin_bit_cast(double, (static_cast<long long>(hi[1]) << 32) | lo[1]);
+    return x2 + y2;
+}
+__device__ __forceinline__ double fold16(double x, double y) {
+    const long long bx = __builtin_bit_cast(long long, x), by = __builtin_bit_cast(long long, y);
+    const auto lo = __builtin_amdgcn_permlane16_swap(unsigned(bx), unsigned(by), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(unsigned(bx >> 32), unsigned(by >> 32), false, false);
+    const double x2 = __builtin_bit_cast(double, (static_cast<long long>(hi[0]) << 32) | lo[0]);
+    const double y2 = __builtin_bit_cast(double, (static_cast<long long>(hi[1]) << 32) | lo[1]);
+    return x2 + y2;
+}
+__device__ __forceinline__ float row_total(float v) {
+    v += dpp_f<0xB1, 0xF>(v);
+    v += dpp_f<0x4E, 0xF>(v);
+    v += dpp_f<0x141, 0xF>(v);
+    v += dpp_f<0x140, 0xF>(v);
+    return v;
+}
+__device__ __forceinline__ double row_total(double v) {
+    v += dpp_d<0xB1, 0xF>(v);
+    v += dpp_d<0x4E, 0xF>(v);
+    v += dpp_d<0x141, 0xF>(v);
+    v += dpp_d<0x140, 0xF>(v);
+    return v;
+}
+template <typename R> __device__ __forceinline__ R totals4(R v0, R v1, R v2, R v3) {
+    return row_total(fold16(fold32(v0, v2), fold32(v1, v3)));
+}
+// the same with the four-row folds in the input precision and the row sums in FP64
+__device__ __forceinline__ double totals4_wide(float v0, float v1, float v2, float v3) {
+    return row_total(double(fold16(fold32(v0, v2), fold32(v1, v3))));
+}
+__device__ __forceinline__ double totals4_wide(double v0, double v1, double v2, double v3) {
+    return totals4(v0, v1, v2, v3);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // 4th-order central differences (+-2 neighbours)
 #define D1C1 (2.0 / 3.0)
 #define D1C2 (-1.0 / 12.0)
@@ -509,21 +572,17 @@ void k_propagate(PropArgs a) {
                         s[3].x += d0z * X0.x + h2z * X1.x;
                         s[3].y += d0z * X0.y + h2z * X1.y;
                     }
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        s[l].x = wave_total(s[l].x);
-                        s[l].y = wave_total(s[l].y);
-                    }
-                    if (lane == 0) {
+                    // row l of (re, im) holds channel l's totals; the first lane of each row stores it
+                    const R re = totals4(s[0].x, s[1].x, s[2].x, s[3].x);
+                    const R im = totals4(s[0].y, s[1].y, s[2].y, s[3].y);
+                    if ((lane & 15) == 0) {
+                        const int l = lane >> 4;
                         const Q4 ap = apar[at];  // N_s, N_p in .z, .w
-#pragma unroll
-                        for (int l = 0; l < 4; ++l) {
-                            const R f = (l == 0) ? ap.z : ap.w;
-                            C v;
-                            v.x = f * s[l].x;
-                            v.y = f * s[l].y;
-                            part[4 * t + l] = v;
-                        }
+                        const R f = (l == 0) ? ap.z : ap.w;
+                        C v;
+                        v.x = f * re;
+                        v.y = f * im;
+                        part[4 * t + l] = v;
                     }
                 }
                 __syncthreads();
@@ -803,19 +862,34 @@ void k_propagate(PropArgs a) {
                     qq[4].x += f0 * d2 * x.x; qq[4].y += f0 * d2 * x.y;
                     qq[5].x += f1 * d2 * x.x; qq[5].y += f1 * d2 * x.y;
                 }
+                // totals of the 20 moment components, four per register (row r of g[i]
+                // holds component 4 i + r), then read out of the rows' first lanes
+                const double g0 = totals4_wide(cs.x, cs.y, cp[0].x, cp[0].y);
+                const double g1 = totals4_wide(cp[1].x, cp[1].y, cp[2].x, cp[2].y);
+                const double g2 = totals4_wide(qq[0].x, qq[0].y, qq[1].x, qq[1].y);
+                const double g3 = totals4_wide(qq[2].x, qq[2].y, qq[3].x, qq[3].y);
+                const double g4 = totals4_wide(qq[4].x, qq[4].y, qq[5].x, qq[5].y);
                 double2 tcs, tcp[3], tqq[6];
-                tcs.x = wave_total_wide(cs.x);
-                tcs.y = wave_total_wide(cs.y);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    tcp[i].x = wave_total_wide(cp[i].x);
-                    tcp[i].y = wave_total_wide(cp[i].y);
-                }
-#pragma unroll
-                for (int i = 0; i < 6; ++i) {
-                    tqq[i].x = wave_total_wide(qq[i].x);
-                    tqq[i].y = wave_total_wide(qq[i].y);
-                }
+                tcs.x = readlane_d(g0, 0);
+                tcs.y = readlane_d(g0, 16);
+                tcp[0].x = readlane_d(g0, 32);
+                tcp[0].y = readlane_d(g0, 48);
+                tcp[1].x = readlane_d(g1, 0);
+                tcp[1].y = readlane_d(g1, 16);
+                tcp[2].x = readlane_d(g1, 32);
+                tcp[2].y = readlane_d(g1, 48);
+                tqq[0].x = readlane_d(g2, 0);
+                tqq[0].y = readlane_d(g2, 16);
+                tqq[1].x = readlane_d(g2, 32);
+                tqq[1].y = readlane_d(g2, 48);
+                tqq[2].x = readlane_d(g3, 0);
+                tqq[2].y = readlane_d(g3, 16);
+                tqq[3].x = readlane_d(g3, 32);
+                tqq[3].y = readlane_d(g3, 48);
+                tqq[4].x = readlane_d(g4, 0);
+                tqq[4].y = readlane_d(g4, 16);
+                tqq[5].x = readlane_d(g4, 32);
+                tqq[5].y = readlane_d(g4, 48);
                 const double Es = par[0], Ep = par[1];
                 const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 #pragma unroll
