@@ -194,7 +194,7 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, ab, wacc, ptp, ptk, ptg, rho, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, ptp, ptk, ptg, rho, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -216,6 +216,8 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.t2e = o; o = al16(o + c * (3 * nmaxd + 3));
     L.apar = o; o = al16(o + 4 * r * na);
     L.part = o; o = al16(o + c * 4 * (ntask_max > 0 ? ntask_max : 1));
+    L.tsk = o; o = al16(o + 8 * size_t(ntask_max > 0 ? ntask_max : 1));  // task list
+    L.atk = o; o = al16(o + 4 * size_t(na + 1));                        // first task of each atom
     L.ab = o; o = al16(o + 2 * c * nc);                  // scatter coefficients per column image
     L.wacc = o; o = al16(o + 8 * 4 * size_t(block / 64));  // FP64 current partial per wave
     // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
@@ -334,6 +336,8 @@ void k_propagate(PropArgs a) {
     C *t2e = reinterpret_cast<C *>(smem + L.t2e);           // same, kappa(t_{n+1})
     Q4 *apar = reinterpret_cast<Q4 *>(smem + L.apar);       // Es dV, Ep dV, Ns, Np per atom
     C *part = reinterpret_cast<C *>(smem + L.part);
+    int2 *task_l = reinterpret_cast<int2 *>(smem + L.tsk);
+    int *atk_l = reinterpret_cast<int *>(smem + L.atk);
     Q4 *AB = reinterpret_cast<Q4 *>(smem + L.ab);           // scatter coefficients A, B per column image
     double *wacc = reinterpret_cast<double *>(smem + L.wacc);  // current partial per wave (x, y, z, -)
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
@@ -407,6 +411,8 @@ void k_propagate(PropArgs a) {
         q.w = R(par[3]);
         apar[at] = q;
     }
+    for (int i = tid; i <= nat; i += BS) atk_l[i] = I.atom_task[i];
+    for (int i = tid; i < ntask; i += BS) task_l[i] = gld(task + i);
 
     if (SL) {
         const auto *p16 = gview(I.pt_ptr16);
@@ -534,7 +540,7 @@ void k_propagate(PropArgs a) {
                 //   sum g d e^{i kappa.d} w = colphase (d_0 X0 + (a_3/N3) X1),
                 //   d_0 = dcol + j2_0 a_3/N3 (the first point's offset), X0 = sum x_i, X1 = sum i x_i.
                 for (int t = wave; t < ntask; t += NW) {
-                    const int2 tk = gld(task + t);
+                    const int2 tk = task_l[t];
                     const int c0 = tk.x, cnt = tk.y >> 8, at = tk.y & 255;
                     C s[4];
 #pragma unroll
@@ -597,7 +603,7 @@ void k_propagate(PropArgs a) {
                     C e[4];
 #pragma unroll
                     for (int l = 0; l < 4; ++l) { e[l].x = R(0); e[l].y = R(0); }
-                    for (int t = atom_task[at]; t < atom_task[at + 1]; ++t) {
+                    for (int t = atk_l[at]; t < atk_l[at + 1]; ++t) {
 #pragma unroll
                         for (int l = 0; l < 4; ++l) {
                             const C v = part[4 * t + l];
