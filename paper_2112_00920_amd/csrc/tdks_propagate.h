@@ -516,20 +516,22 @@ void k_propagate(PropArgs a) {
             C *ug = reinterpret_cast<C *>(I.u) + orb;
             const C *src = (a.mode == MODE_APPLY) ? reinterpret_cast<const C *>(a.apply_in) + orb : ug;
             C acc[ZL], wc[ZL];
-            __syncthreads();  // previous users of W (and the phase tables) are done
             const int pl = opq(pbase + plane * z0);
+            // the orbital's loads are issued before the barrier, so their latency overlaps
+            // the wait for the other waves
 #pragma unroll
             for (int z = 0; z < ZL; ++z) {
                 C v;
                 v.x = R(0);
                 v.y = R(0);
-                if (active) {
-                    const int p = pl + plane * z;
-                    v = gld(src + p);
-                    W[p] = v;
-                }
+                if (active) v = gld(src + pl + plane * z);
                 acc[z] = v;
                 wc[z] = v;
+            }
+            __syncthreads();  // previous users of W (and the phase tables) are done
+            if (active) {
+#pragma unroll
+                for (int z = 0; z < ZL; ++z) W[pl + plane * z] = acc[z];
             }
 
 #pragma unroll 1
