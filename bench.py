@@ -35,7 +35,7 @@ FP32_VECTOR_PEAK_TF = 157.3    # MI355X published FP32 vector peak
 FP64_VECTOR_PEAK_TF = 78.6
 # Algorithmic work per update (one grid point of one orbital advanced one Taylor-4 step):
 BYTES_PER_UPDATE = {"fp32": 16.0, "fp64": 32.0}   # read u once, write u once
-FLOPS_PER_UPDATE = 710.0                          # stencil + potential + projectors + FP64 sums
+FLOPS_PER_UPDATE = 700.0  # 4 x (stencil 75 + projectors 65 + Taylor 4) + density 5 + current 122
 
 
 def log(msg):
