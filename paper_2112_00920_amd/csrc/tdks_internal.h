@@ -75,6 +75,9 @@ struct WorkItem {
 #define TDKS_PROPAGATE_CONFIGS(X) \
     X(2, 512, 2) X(3, 512, 2) X(4, 512, 2) X(6, 512, 2) X(8, 512, 2) X(12, 512, 2) X(16, 512, 2) \
     X(4, 512, 4) X(6, 512, 4) X(8, 512, 4) X(4, 1024, 4) X(8, 1024, 4) X(10, 1024, 4)
+// tilings whose last z-segment of a column may be shorter (N3 not a multiple of ZL)
+#define TDKS_PROPAGATE_RAGGED_CONFIGS(X) \
+    X(4, 512, 4) X(4, 1024, 4) X(8, 512, 2) X(8, 1024, 4) X(10, 1024, 4)
 
 enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2 };
 
@@ -99,9 +102,9 @@ struct PropArgs {
 
 // Host-side launchers implemented in tdks_kernels.hip.
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
-                            int nonorth, int sl, hipStream_t s);
+                            int nonorth, int sl, int ragged, hipStream_t s);
 size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block);
-bool propagate_config_ok(int block, int zl, int minw);
+bool propagate_config_ok(int block, int zl, int minw, int ragged);
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
                          double *jout, int jstride, const int *rec_ctr, hipStream_t s);
 hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const double *rho,

@@ -4,30 +4,34 @@
 
 namespace tdks {
 
-hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, int, int, hipStream_t);
-hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
 
 size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block) {
     return propagate_lds_bytes_inl(fp64, sl, a, block);
 }
 
-bool propagate_config_ok(int block, int zl, int minw) {
+bool propagate_config_ok(int block, int zl, int minw, int ragged) {
     if (block < 64 || block > 1024 || (block & 63)) return false;
 #define TDKS_OK_CASE(Z, M, O) if (zl == Z && block <= M && minw == O) return true;
-    TDKS_PROPAGATE_CONFIGS(TDKS_OK_CASE)
+    if (ragged) {
+        TDKS_PROPAGATE_RAGGED_CONFIGS(TDKS_OK_CASE)
+    } else {
+        TDKS_PROPAGATE_CONFIGS(TDKS_OK_CASE)
+    }
 #undef TDKS_OK_CASE
     return false;
 }
 
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
-                            int nonorth, int sl, hipStream_t s) {
+                            int nonorth, int sl, int ragged, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, minw, sl, s)
-                             : launch_propagate_f64_orth(a, n_items, block, zl, minw, sl, s);
-    return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, minw, sl, s)
-                   : launch_propagate_f32_orth(a, n_items, block, zl, minw, sl, s);
+    if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
+                             : launch_propagate_f64_orth(a, n_items, block, zl, minw, sl, ragged, s);
+    return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
+                   : launch_propagate_f32_orth(a, n_items, block, zl, minw, sl, ragged, s);
 }
 
 // ---------------------------------------------------------------------------

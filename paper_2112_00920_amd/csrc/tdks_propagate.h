@@ -305,7 +305,7 @@ template <> __device__ __forceinline__ const float *ptgtab<float>(const DevInst 
 template <> __device__ __forceinline__ const double *ptgtab<double>(const DevInst &I) { return I.pt_gd; }
 
 
-template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL>
+template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL, bool RAGGED>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -358,10 +358,13 @@ void k_propagate(PropArgs a) {
     const auto *atom_task = gview(I.atom_task);
     const auto *kcart = gview(I.kcart);
     const int plane = N0 * N1;
-    const int nseg = N2 / ZL;
+    // z-segments of ZL points; with RAGGED the last one of a column is shorter (N3 % ZL)
+    const int nseg = RAGGED ? (N2 + ZL - 1) / ZL : N2 / ZL;
     const bool active = tid < plane * nseg;
     const int i0 = tid % N0, i1 = (tid / N0) % N1, seg = tid / plane;
     const int z0 = seg * ZL;
+    const int zlen = RAGGED ? min(ZL, N2 - z0) : ZL;  // points of this thread's segment
+#define TDKS_ZOK(z) (!RAGGED || (z) < zlen)
     const int pbase = i0 + N0 * i1;  // p(z) = pbase + plane * z
     // in-plane neighbour offsets: +1, -1, +2, -2 along a_1 and a_2 (periodic)
     int ox[4], oy[4];
@@ -426,7 +429,7 @@ void k_propagate(PropArgs a) {
     R vz[ZL];
 #pragma unroll
     for (int z = 0; z < ZL; ++z) {
-        vz[z] = active ? vtot[pbase + plane * (z0 + z)] : R(0);
+        vz[z] = (active && TDKS_ZOK(z)) ? vtot[pbase + plane * (z0 + z)] : R(0);
     }
 
     // Laplacian coefficients (metric only)
@@ -524,14 +527,15 @@ void k_propagate(PropArgs a) {
                 C v;
                 v.x = R(0);
                 v.y = R(0);
-                if (active) v = gld(src + pl + plane * z);
+                if (active && TDKS_ZOK(z)) v = gld(src + pl + plane * z);
                 acc[z] = v;
                 wc[z] = v;
             }
             __syncthreads();  // previous users of W (and the phase tables) are done
             if (active) {
 #pragma unroll
-                for (int z = 0; z < ZL; ++z) W[pl + plane * z] = acc[z];
+                for (int z = 0; z < ZL; ++z)
+                    if (TDKS_ZOK(z)) W[pl + plane * z] = acc[z];
             }
 
 #pragma unroll 1
@@ -643,7 +647,7 @@ void k_propagate(PropArgs a) {
                 for (int z = 0; z < ZL; ++z) {
                     hz[z].x = R(0);
                     hz[z].y = R(0);
-                    if (!active) continue;
+                    if (!active || !TDKS_ZOK(z)) continue;
                     const int zg = z0 + z;
                     const int p = pb + plane * zg;
                     // z neighbours: registers inside the segment, LDS across segment ends
@@ -652,9 +656,9 @@ void k_propagate(PropArgs a) {
                     for (int s = 0; s < 4; ++s) {
                         const int dz = (s == 0) ? 1 : (s == 1) ? -1 : (s == 2) ? 2 : -2;
                         const int zz = z + dz;
-                        if (zz >= 0 && zz < ZL) {
+                        if (zz >= 0 && zz < ZL && (!RAGGED || zz < zlen)) {
                             zn[s] = wc[zz];
-                        } else if (nseg == 1) {
+                        } else if (nseg == 1 && !RAGGED) {
                             zn[s] = wc[(zz + ZL) % ZL];
                         } else {
                             int zw = zg + dz;
@@ -746,7 +750,8 @@ void k_propagate(PropArgs a) {
                     C *out = reinterpret_cast<C *>(a.apply_out) + orb;
                     if (active) {
 #pragma unroll
-                        for (int z = 0; z < ZL; ++z) gst(out + pw + plane * z, hz[z]);
+                        for (int z = 0; z < ZL; ++z)
+                            if (TDKS_ZOK(z)) gst(out + pw + plane * z, hz[z]);
                     }
                 } else {
                     const R cm = R(a.dt / m);
@@ -758,7 +763,7 @@ void k_propagate(PropArgs a) {
                         acc[z].x += wn.x;
                         acc[z].y += wn.y;
                         wc[z] = wn;
-                        if (active) W[pw + plane * z] = wn;
+                        if (active && TDKS_ZOK(z)) W[pw + plane * z] = wn;
                     }
                 }
             }
@@ -774,6 +779,7 @@ void k_propagate(PropArgs a) {
                 const bool first = (kk == 0) && (bb == 0);
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
+                    if (!TDKS_ZOK(z)) continue;
                     const int p = ps + plane * z;
                     W[p] = acc[z];
                     if (a.mode == MODE_STEP) gst(ug + p, acc[z]);
@@ -797,6 +803,7 @@ void k_propagate(PropArgs a) {
             if (active) {
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
+                    if (!TDKS_ZOK(z)) continue;
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
                     const C u = W[p];
@@ -933,7 +940,8 @@ void k_propagate(PropArgs a) {
         auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
         const int pr = opq(pbase + plane * z0);
 #pragma unroll
-        for (int z = 0; z < ZL; ++z) rp[pr + plane * z] = RHO[pr + plane * z];
+        for (int z = 0; z < ZL; ++z)
+            if (TDKS_ZOK(z)) rp[pr + plane * z] = RHO[pr + plane * z];
     }
     __syncthreads();
     if (tid < 3) {
@@ -943,6 +951,7 @@ void k_propagate(PropArgs a) {
         jp[tid] = s;
         if (tid == 0) jp[3] = 0.0;
     }
+#undef TDKS_ZOK
 }
 
 }  // namespace tdks

@@ -94,7 +94,7 @@ struct InstHost {
 struct ShapeClass {
     int N[3];
     bool nonorth;
-    int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0;
+    int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0;
     int wbeg = 0, wend = 0;
     int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0, plane_max = 0;
 };
@@ -449,7 +449,8 @@ int upload(tdks_ctx *c, T **dst, const std::vector<T> &src) {
     } while (0)
 
 // choose the column-segment length, block and occupancy target for one grid shape
-bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl, int &block, int &minw) {
+bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl, int &block, int &minw,
+                   int &ragged) {
     static const int zls[] = {2, 3, 4, 6, 8, 10, 12, 16};
     // measured on MI355X: FP32 runs best with short segments and 4 waves per SIMD,
     // FP64 with 512-thread blocks at 2 waves per SIMD (see the autotuner for other shapes)
@@ -457,21 +458,25 @@ bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl
     int best_cost = 1 << 30;
     bool found = false;
     for (int z : zls) {
-        if (N[2] % z) continue;
-        int b = N[0] * N[1] * (N[2] / z);
+        // segments of z points along a_3; if z does not divide N3 the last one of each column
+        // is shorter (only some tilings are built for that)
+        const int rg = (N[2] % z) ? 1 : 0;
+        const int nseg = (N[2] + z - 1) / z;
+        int b = N[0] * N[1] * nseg;
         b = (b + 63) / 64 * 64;
         // more than 512 threads need 4 waves per SIMD; otherwise short FP32 segments fit the
         // 128-register budget of 4 waves, longer ones (and FP64) run at 2
         int w = (b > 512) ? 4 : (want_w > 0 ? want_w : ((!fp64 && z <= 4) ? 4 : 2));
-        if (!propagate_config_ok(b, z, w)) w = (w == 4) ? 2 : 4;
-        if (!propagate_config_ok(b, z, w)) continue;
-        int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0);
-        if (want_block > 0) cost = std::abs(b - want_block) * 16 + std::abs(z - target);
+        if (!propagate_config_ok(b, z, w, rg)) w = (w == 4) ? 2 : 4;
+        if (!propagate_config_ok(b, z, w, rg)) continue;
+        int cost = std::abs(z - target) * 4 + (b < 128 ? 2 : 0) + rg * 16;
+        if (want_block > 0) cost = std::abs(b - want_block) * 16 + std::abs(z - target) + rg * 16;
         if (cost < best_cost) {
             best_cost = cost;
             zl = z;
             block = b;
             minw = w;
+            ragged = rg;
             found = true;
         }
     }
@@ -519,7 +524,8 @@ int enqueue_step(tdks_ctx *c) {
     for (const ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
         a.work = c->d_work + S.wbeg;
-        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
+                                c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
                          c->d_ctrs + 1, c->stream));
@@ -606,7 +612,8 @@ int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jds
         if (we <= wb) continue;
         PropArgs a = class_args(c, S, MODE_OBSERVE, c->d_Aobs, c->d_ctrs + 2);
         a.work = c->d_work + wb;
-        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
+        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
+                                c->stream));
     }
     HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
                          c->stream));
@@ -719,7 +726,8 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
             ShapeClass S;
             for (int q = 0; q < 3; ++q) S.N[q] = I.N[q];
             S.nonorth = I.nonorth;
-            if (!choose_tiling(S.N, c->fp64, opt->block_size, opt->waves_per_simd, S.zl, S.block, S.minw))
+            if (!choose_tiling(S.N, c->fp64, opt->block_size, opt->waves_per_simd, S.zl, S.block, S.minw,
+                               S.ragged))
                 return fail(TDKS_E_UNSUPPORTED, "no built propagation tiling for grid %dx%dx%d", S.N[0], S.N[1], S.N[2]);
             c->classes.push_back(S);
             cls = int(c->classes.size()) - 1;
@@ -1139,7 +1147,8 @@ int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, i
     a.work = c->d_work + I.wbeg;
     a.apply_in = win;
     a.apply_out = wout;
-    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
+    HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
+                            c->stream));
     HIPCHK(launch_convert_out(wout, stage, n, c->fp64, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(hw, stage, 16 * n, where == TDKS_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice));
@@ -1172,7 +1181,8 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
         for (const ShapeClass &S : c->classes) {
             PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
             a.work = c->d_work + S.wbeg;
-            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, c->stream));
+            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
+                                c->stream));
         }
         HIPCHK(hipEventRecord(ev[3 * s + 1], c->stream));
         HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),

@@ -1,6 +1,7 @@
 """Edge cases of the GPU path, through the C ABI: zero-step and split calls, a
 single band at the Gamma point on a small grid, a k-point on
-the zone boundary, two species, the longest grid axis the kernels accept, and the
+the zone boundary, two species, the longest grid axis the kernels accept, grids
+whose a_3 size the z-segment length does not divide (ragged segments), and the
 state error of stepping before loading."""
 import sys
 
@@ -135,3 +136,31 @@ def test_step_before_load_is_a_state_error(tdks):
         with pytest.raises(_lib.TdksError) as e:
             p.step(W.Field("kick", 1e-3).table(1, 0.02))
         assert e.value.code == _lib.E_STATE
+
+
+RAGGED_CASES = {
+    # grids whose a_3 size is not a multiple of the chosen z-segment length
+    "d8_15": ("diamond8", (15, 15, 15), 2, W.KSpec((1, 1, 2))),  # the paper's grid size
+    "d8_7": ("diamond8", (7, 7, 7), 3, W.KSpec((2, 1, 1))),
+    "d8_12x12x13": ("diamond8", (12, 12, 13), 2, W.KSpec((1, 1, 1))),
+    "fcc2_7": ("fcc2", (7, 7, 7), 2, W.KSpec((2, 2, 1))),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(RAGGED_CASES))
+def test_ragged_z_segments(tdks, name, precision):
+    cell, grid, nb, ks = RAGGED_CASES[name]
+    inst = W.make_instance(cell, grid, nb, [_species()], ks)
+    nk = int(np.prod(ks.coarse))
+    u0 = W.random_orbitals(16, nk, nb, grid, inst.omega)
+    A = W.Field("kick", 1e-3).table(4, 0.02)
+    with tdks.Propagator([inst], precision=precision) as p:
+        til = p.tiling()
+        p.load_orbitals(0, u0)
+        p.step(A)
+        dj, u = p.current()[0], p.get_orbitals(0)
+    _say(f"  {name} {precision}: tiling {til}")
+    assert grid[2] % til["zl"] != 0 or grid[2] < til["zl"]
+    dj_o, u_o = _oracle(inst, u0, A)
+    _check(name, dj, u, dj_o, u_o, precision)
