@@ -3,10 +3,10 @@
 Candidates: the z-segment length per thread (through the block size
 N1 N2 N3 / ZL), the occupancy target (waves per SIMD, i.e. the register
 budget), bands per workgroup and k-points per workgroup.  Each candidate is
-timed with HIP events on a sample of the workload (the first instance of each
-grid shape, a slice of its k-points) for a few steps; the fastest per update
-wins.  Results are cached in a JSON file keyed by the grid shapes, band counts
-and precision.
+timed with HIP events on a sample of the workload (instances of the most common
+grid shape with at least `min_items` k-points in all, so that the sample fills the
+GPU as the workload does) for a few steps; the fastest per update wins.  Results
+are cached in a JSON file keyed by the grid shapes, band counts and precision.
 """
 from __future__ import annotations
 
@@ -32,9 +32,8 @@ def candidates(inst, precision) -> List[Dict]:
     out = []
     blocks = []
     for z in _ZLS:
-        if N3 % z:
-            continue
-        b = (N1 * N2 * (N3 // z) + 63) // 64 * 64
+        nseg = -(-N3 // z)  # the last segment of a column may be shorter
+        b = (N1 * N2 * nseg + 63) // 64 * 64
         if 64 <= b <= 1024:
             blocks.append(b)
     for b in sorted(set(blocks)):
@@ -45,9 +44,13 @@ def candidates(inst, precision) -> List[Dict]:
     return out
 
 
-def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, k_sample: int = 64,
+def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, min_items: int = 2048,
          cache: Optional[str] = DEFAULT_CACHE, verbose: bool = False, max_candidates: int = 12) -> Dict:
-    """Returns the Propagator tiling options with the best measured updates/s."""
+    """Returns the Propagator tiling options with the best measured updates/s.
+
+    The sample is the instances of the most common grid shape, as many as it takes to
+    reach `min_items` k-points (so that the sample fills the GPU the way the workload
+    does), with their full k-sets."""
     import torch
     import workloads as W
     from . import Propagator
@@ -61,21 +64,31 @@ def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, k_sample:
                 return stored[key]["options"]
         except (OSError, ValueError):
             pass
-    # sample: the first instance of the most common grid shape, with a slice of its k-points
     shapes = {}
     for inst in instances:
         shapes.setdefault(tuple(inst.grid), []).append(inst)
-    main = max(shapes.values(), key=len)[0]
-    from .kpoints import from_spec
-    kf = from_spec(main.kspec)[:k_sample]
-    u = W.random_orbitals_torch(7, len(kf), main.n_bands, main.grid, main.omega)
+    group = max(shapes.values(), key=len)
+    sample, nk = [], 0
+    for inst in group:
+        sample.append(inst)
+        nk += inst.n_k
+        if nk >= min_items:
+            break
+    us = [W.random_orbitals_torch(7 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+          for i, inst in enumerate(sample)]
     A = W.Field("kick", 1e-3).table(steps + 2, 0.02)
-    upd = len(kf) * main.n_bands * main.ng
-    results = []
-    for opts in candidates(main, precision)[:max_candidates]:
+    upd = sum(inst.n_k * inst.n_bands * inst.ng for inst in sample)
+    results, seen = [], set()
+    for opts in candidates(sample[0], precision)[:max_candidates]:
         try:
-            with Propagator([main], k_fracs=[kf], precision=precision, **opts) as p:
-                p.load_orbitals(0, u)
+            with Propagator(sample, precision=precision, **opts) as p:
+                til = p.tiling()
+                sig = (til["block"], til["zl"], til["waves_per_simd"], til["bands_per_group"], til["k_per_group"])
+                if sig in seen:  # the library maps this request onto a tiling already measured
+                    continue
+                seen.add(sig)
+                for i, u in enumerate(us):
+                    p.load_orbitals(i, u)
                 p.step(A[:2])
                 t = p.time_kernels(A[2:2 + steps])["propagate_ms"]
         except Exception as exc:  # a tiling the library rejects for this shape
@@ -85,8 +98,8 @@ def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, k_sample:
         rate = upd / (t * 1e-3)
         results.append((rate, opts))
         if verbose:
-            print(f"autotune: {opts} -> {rate:.3e} updates/s")
-    del u
+            print(f"autotune: {opts} (tiling {til}) -> {rate:.3e} updates/s")
+    del us
     torch.cuda.empty_cache()
     if not results:
         return {}
