@@ -141,8 +141,12 @@ void tdks_default_options(tdks_options *opt);
  * support tables and the k tables on the host, allocates the device memory
  * through opt->alloc, and returns the context in *out.
  * Errors: E_ARG (bad descriptor, e.g. Rc too large for the cell), E_OOM,
- * E_HIP, E_UNSUPPORTED (grid larger than 8192 points, N_d > 64, more than
- * 64 atoms, taylor_order != 4). */
+ * E_HIP, E_UNSUPPORTED (an axis outside 4..32 points or more than 8192 grid
+ * points, more than 64 atoms, more than 4095 projector column images or 65535
+ * support entries, a grid whose orbital and projector tables do not fit the
+ * 160 KB of LDS of one workgroup at the requested precision -- FP64 on 20^3,
+ * for instance --, taylor_order != 4).  All of these are detected on the host
+ * before any device call. */
 int tdks_create(const tdks_instance_desc *inst, int n_inst, const tdks_options *opt,
                 tdks_ctx **out);
 
