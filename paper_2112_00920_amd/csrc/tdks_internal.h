@@ -37,7 +37,7 @@ struct DevInst {
     int ncol;                  // column images
     const int *col_atom;       // [ncol] atom of each column image
     const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8 | (r + 128) << 16
-    const uint32_t *ent_pack;  // atom-major entries: p | (j2 - r + N3) << 13 | col << 20
+    const uint32_t *ent_pack;  // atom-major entries: p | (j2 - r + N3 + 3) << 13 | col << 20
     const float *ent_gf;       // radial factor g(|d|) of each entry, FP32 copy
     const double *ent_gd;      // ... FP64 copy
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point

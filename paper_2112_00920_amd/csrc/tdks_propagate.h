@@ -184,7 +184,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 #define D2C1 (4.0 / 3.0)
 #define D2C2 (-1.0 / 12.0)
 
-// packed projector entry: grid index p | (j2 + N3) << 13 | column image << 20 (j2 counted
+// packed projector entry: grid index p | (j2 + N3 + 3) << 13 | column image << 20 (j2 counted
 // from the column image's reference step)
 __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &col) {
     p = int(v & 8191u);
@@ -208,12 +208,12 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     const int nc = ncol_max > 0 ? ncol_max : 1;
     PropLds L;
     size_t o = 0;
-    L.W = o; o = al16(o + c * (ng_max + 3 * size_t(plane_max)));  // + zeroed slack read by padded chunks
+    L.W = o; o = al16(o + c * size_t(ng_max));
     L.cold = o; o = al16(o + 4 * r * nc);
     L.colm = o; o = al16(o + c * nc);
     L.cole = o; o = al16(o + c * nc);
-    L.t2m = o; o = al16(o + c * (3 * nmaxd + 3));
-    L.t2e = o; o = al16(o + c * (3 * nmaxd + 3));
+    L.t2m = o; o = al16(o + c * (3 * nmaxd + 6));
+    L.t2e = o; o = al16(o + c * (3 * nmaxd + 6));
     L.apar = o; o = al16(o + 4 * r * na);
     L.part = o; o = al16(o + c * 4 * (ntask_max > 0 ? ntask_max : 1));
     L.tsk = o; o = al16(o + 8 * size_t(ntask_max > 0 ? ntask_max : 1));  // task list
@@ -358,6 +358,7 @@ void k_propagate(PropArgs a) {
     const auto *atom_task = gview(I.atom_task);
     const auto *kcart = gview(I.kcart);
     const int plane = N0 * N1;
+    const int j2off = N2 + 3;  // stored a_3 steps are j2 + N3 + 3 (j2 counted from the reference step)
     // z-segments of ZL points; with RAGGED the last one of a column is shorter (N3 % ZL)
     const int nseg = RAGGED ? (N2 + ZL - 1) / ZL : N2 / ZL;
     const bool active = tid < plane * nseg;
@@ -379,12 +380,6 @@ void k_propagate(PropArgs a) {
 
     const double *Am = a.A_tab + 6 * (*a.step_ctr);
     for (int i = tid; i < 4 * NW; i += BS) wacc[i] = 0.0;
-    for (int i = tid; i < 3 * N0 * N1; i += BS) {  // slack after the orbital, read (times g = 0) by padded chunks
-        C zero;
-        zero.x = R(0);
-        zero.y = R(0);
-        W[ng + i] = zero;
-    }
     const double dV = I.dV;
     const int nat = I.nat;
     const int ntask = I.ntask;
@@ -498,10 +493,10 @@ void k_propagate(PropArgs a) {
         {
             const double thm = (km[0] * I.hv[2][0] + km[1] * I.hv[2][1] + km[2] * I.hv[2][2]) * inv_pi;
             const double the = (ke[0] * I.hv[2][0] + ke[1] * I.hv[2][1] + ke[2] * I.hv[2][2]) * inv_pi;
-            for (int j = tid; j < 3 * N2 + 3; j += BS) {
+            for (int j = tid; j < 3 * N2 + 6; j += BS) {
                 double sm, cm, se, ce;
-                sincospi(double(j - N2) * thm, &sm, &cm);
-                sincospi(double(j - N2) * the, &se, &ce);
+                sincospi(double(j - j2off) * thm, &sm, &cm);
+                sincospi(double(j - j2off) * the, &se, &ce);
                 C t;
                 t.x = R(cm);
                 t.y = R(sm);
@@ -573,7 +568,7 @@ void k_propagate(PropArgs a) {
                         const C ph = colm[col];
                         const Q4 cd = cold[col];
                         const C X0 = cmul(ph, y0), X1 = cmul(ph, y1);
-                        const R j20 = R(j2u0 - N2);
+                        const R j20 = R(j2u0 - j2off);
                         const R d0x = cd.x + j20 * h2x, d0y = cd.y + j20 * h2y, d0z = cd.z + j20 * h2z;
                         s[0].x += X0.x;
                         s[0].y += X0.y;
@@ -735,7 +730,7 @@ void k_propagate(PropArgs a) {
                         const R gv = SL ? ptg_l[e] : pgt[e];
                         const Q4 q = AB[col];
                         const C t2 = t2m[j2u];
-                        const R j2 = R(j2u - N2);
+                        const R j2 = R(j2u - j2off);
                         C s;
                         s.x = (q.x + j2 * q.z) * gv;
                         s.y = (q.y + j2 * q.w) * gv;
@@ -860,7 +855,7 @@ void k_propagate(PropArgs a) {
                     const Q4 cd = cold[col];
                     const C ph = cmul(cole[col], t2e[j2u]);
                     const C x = cmul(ph, W[p]);
-                    const R j2 = R(j2u - N2);
+                    const R j2 = R(j2u - j2off);
                     const R d0 = cd.x + j2 * h2x, d1 = cd.y + j2 * h2y, d2 = cd.z + j2 * h2z;
                     const R fs = rns * gv, fp = rnp * gv;
                     cs.x += fs * x.x;

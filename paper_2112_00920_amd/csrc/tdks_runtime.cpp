@@ -315,7 +315,7 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                 if (r < -127 || r > 127) return fail(TDKS_E_UNSUPPORTED, "atom %d: column reference out of range", a);
                 colref[kv.first] = r;
                 for (auto &e : kv.second) {
-                    const int f = e.first - r;  // (j2 - r) + N3 with j2 = u2 - N3
+                    const int f = e.first - r;  // (j2 - r) + N3 with j2 = u2 - N3; stored + 3
                     if (f < 0 || f >= 2 * I.N[2])
                         return fail(TDKS_E_ARG, "atom %d: projector support spans more than the cell along a_3", a);
                 }
@@ -340,14 +340,21 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                     Ch c{};
                     const int u2 = pts[i].first, p = pts[i].second.first;
                     c.key = (static_cast<long long>(u2) << 16) | ((kv.first >> 8) << 8) | (kv.first & 255);
-                    c.pack = uint32_t(p) | (uint32_t(u2 - colref[kv.first]) << 13) | (uint32_t(col) << 20);
+                    double g[4] = {0.0, 0.0, 0.0, 0.0};
                     int n = 0;
                     while (n < 4 && i < pts.size() && pts[i].first == u2 + n &&
                            (n == 0 || pts[i].second.first == p + n * I.N[0] * I.N[1])) {
-                        c.g[n] = pts[i].second.second;
+                        g[n] = pts[i].second.second;
                         ++n;
                         ++i;
                     }
+                    // a chunk reads 4 consecutive grid planes: one that would run past the last
+                    // plane starts lower, with g = 0 on the points ahead of its own
+                    const int plane = I.N[0] * I.N[1];
+                    const int sh = std::max(0, p / plane + 4 - I.N[2]);
+                    for (int q = 0; q < 4; ++q) c.g[q] = (q >= sh) ? g[q - sh] : 0.0;
+                    c.pack = uint32_t(p - sh * plane) | (uint32_t(u2 - sh - colref[kv.first] + 3) << 13) |
+                             (uint32_t(col) << 20);
                     chs.push_back(c);
                 }
                 ++col;
@@ -367,7 +374,7 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
             T.col_j01.push_back(kv.first | ((colref[kv.first] + 128) << 16));
             for (auto &e : kv.second) {
                 const long long key = (static_cast<long long>(e.first) << 16) | ((kv.first >> 8) << 8) | (kv.first & 255);
-                order.push_back({key, Ent{col, e.first - colref[kv.first], e.second.first, e.second.second}});
+                order.push_back({key, Ent{col, e.first - colref[kv.first] + 3, e.second.first, e.second.second}});
             }
         }
         std::sort(order.begin(), order.end(), [](const std::pair<long long, Ent> &x,
