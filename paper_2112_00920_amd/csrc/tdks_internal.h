@@ -10,7 +10,6 @@ namespace tdks {
 constexpr int kMaxAtoms = 64;
 constexpr int kMaxGridDim = 32;   // N_d <= 32 (DFT lines held in registers; packed j_d + N_d < 256)
 constexpr int kMaxPoints = 8192;  // N1 N2 N3 <= 8192 (one orbital per workgroup in LDS)
-constexpr int kTaskLen = 128;     // projector entries per projection task (two per lane)
 
 // Per-instance data visible to the kernels (lives in device memory).
 struct DevInst {

@@ -194,7 +194,7 @@ __device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &co
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, ptp, ptk, ptg, rho, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, nlm, ptp, ptk, ptg, rho, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -220,6 +220,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.atk = o; o = al16(o + 4 * size_t(na + 1));                        // first task of each atom
     L.ab = o; o = al16(o + 2 * c * nc);                  // scatter coefficients per column image
     L.wacc = o; o = al16(o + 8 * 4 * size_t(block / 64));  // FP64 current partial per wave
+    L.nlm = o; o = al16(o + 8 * 20 * size_t(ntask_max > 0 ? ntask_max : 1));  // current moments per task
     // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
@@ -305,6 +306,30 @@ template <> __device__ __forceinline__ const float *ptgtab<float>(const DevInst 
 template <> __device__ __forceinline__ const double *ptgtab<double>(const DevInst &I) { return I.pt_gd; }
 
 
+// Non-local current of one atom from the 20 totals m (re, im) of its moments over one orbital,
+// M0 = sum g x, M1_a = sum g d_a x, M2_ab = sum g d_a d_b x (ab = 00 11 22 01 02 12), x the
+// orbital times the conjugate Bloch phase, g the radial factor and d the offset from the atom.
+// With c = <P|u> and c_d = <d P|u> the commutator term is sum_lm 2 E_l Im(conj(c_d,lm) c_lm);
+// for f_s = N_s g and f_p,i = N_p g d_i that is, per axis a,
+//   E_s N_s^2 Im(conj(M1_a) M0) + E_p N_p^2 sum_i Im(conj(M2_ia) M1_i).
+// Adds scale times it to j.
+__device__ __forceinline__ void nl_current(const double *m, double Es, double Ep, double ns, double np,
+                                           double scale, double *j) {
+    const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    const double ws = Es * ns * ns, wp = Ep * np * np;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double px = m[2 + 2 * d], py = m[3 + 2 * d];
+        double v = ws * (px * m[1] - py * m[0]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int q = qi[i][d];
+            v += wp * (m[8 + 2 * q] * m[3 + 2 * i] - m[9 + 2 * q] * m[2 + 2 * i]);
+        }
+        j[d] += scale * v;
+    }
+}
+
 template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL, bool RAGGED>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
@@ -340,6 +365,7 @@ void k_propagate(PropArgs a) {
     int *atk_l = reinterpret_cast<int *>(smem + L.atk);
     Q4 *AB = reinterpret_cast<Q4 *>(smem + L.ab);           // scatter coefficients A, B per column image
     double *wacc = reinterpret_cast<double *>(smem + L.wacc);  // current partial per wave (x, y, z, -)
+    double *nlm = reinterpret_cast<double *>(smem + L.nlm);    // non-local current moments per task
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
     uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
     R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
@@ -440,6 +466,30 @@ void k_propagate(PropArgs a) {
     cx[1] = uni(R(-I.g[0][2]));
     cx[2] = uni(R(-I.g[1][2]));
     const int norder = (a.mode == MODE_STEP) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
+    // non-local current of a band: its per-task moment totals are combined per atom (in task
+    // order) after the next barrier, with the band's weight kept in fo_prev
+    double fo_prev = 0.0;
+    bool nl_pending = false;
+    auto nl_combine = [&]() {
+#pragma unroll 1
+        for (int at = wave; at < nat; at += NW) {
+            // lane c < 20 adds up component c over the atom's tasks; the totals are then read
+            // out as wave-uniform values
+            const int c = (lane < 20) ? lane : 0;
+            double s = 0.0;
+            for (int tt = atk_l[at]; tt < atk_l[at + 1]; ++tt) s += nlm[20 * tt + c];
+            double m[20];
+#pragma unroll
+            for (int q = 0; q < 20; ++q) m[q] = readlane_d(s, q);
+            const double *par = I.atom_par + 4 * at;
+            double j[3] = {0.0, 0.0, 0.0};
+            nl_current(m, par[0], par[1], par[2], par[3], 2.0 * dV * dV, j);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) wacc[4 * wave + q] += fo_prev * j[q];
+            }
+        }
+    };
 
 #pragma unroll 1
     for (int kk = 0; kk < w_nk; ++kk) {
@@ -527,6 +577,10 @@ void k_propagate(PropArgs a) {
                 wc[z] = v;
             }
             __syncthreads();  // previous users of W (and the phase tables) are done
+            if (nl_pending) {  // the previous band's split non-local current
+                nl_combine();
+                nl_pending = false;
+            }
             if (active) {
 #pragma unroll
                 for (int z = 0; z < ZL; ++z)
@@ -829,90 +883,81 @@ void k_propagate(PropArgs a) {
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) qn[d] = R(2) * (R(D1C1) * q1[d] + R(D1C2) * q2[d]);
-            // non-local current: one wave per atom.  With c = <P|u>, c_d = <d P|u> the
-            // commutator term is sum_lm 2 E_l Im(conj(c_d,lm) c_lm); since
-            // d_j f_s = (N_s/N_p) f_p,j, only c_s, c_p,i and Q_ij = <d_j P_p,i|u> are needed.
-            double jnl[3] = {0.0, 0.0, 0.0};
+            // non-local current moments of the orbital over the projector chunks (the tasks of
+            // the projections).  On a chunk with x_i = t2(j2_i) u_i g_i and d_i = d_0 + i a_3/N3:
+            //   M0 = ph Y0, M1 = ph (d_0 Y0 + h Y1), M2_ab = ph (d0_a d0_b Y0 + (d0_a h_b + d0_b h_a) Y1
+            //   + h_a h_b Y2), Y_n = sum i^n x_i, h = a_3/N3.  Per-lane sums in the orbital
+            // precision, cross-lane totals in FP64, one row of 20 per task.
+            const R hh[3] = {h2x, h2y, h2z};
 #pragma unroll 1
-            for (int at = wave; at < nat; at += NW) {
-                const int e_beg = I.atom_ent[at], e_end = I.atom_ent[at + 1];
-                const double *par = I.atom_par + 4 * at;
-                const double ns = par[2], np = par[3];
-                // per-lane moment sums in the orbital precision (products of orbital values),
-                // cross-lane totals and everything after them in FP64
-                C cs, cp[3], qq[6];
-                cs.x = R(0);
-                cs.y = R(0);
+            for (int t = wave; t < ntask; t += NW) {
+                const int2 tk = task_l[t];
+                const int c0 = tk.x, cnt = tk.y >> 8;
+                C m0, m1[3], m2[6];
+                m0.x = R(0);
+                m0.y = R(0);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) { cp[i].x = R(0); cp[i].y = R(0); }
+                for (int i = 0; i < 3; ++i) { m1[i].x = R(0); m1[i].y = R(0); }
 #pragma unroll
-                for (int i = 0; i < 6; ++i) { qq[i].x = R(0); qq[i].y = R(0); }
-                const R rns = R(ns), rnp = R(np);
-                for (int e = e_beg + lane; e < e_end; e += 64) {
-                    int p, j2u, col;
-                    ent_unpack(ent_pack[e], p, j2u, col);
-                    const R gv = gt[e];
-                    const Q4 cd = cold[col];
-                    const C ph = cmul(cole[col], t2e[j2u]);
-                    const C x = cmul(ph, W[p]);
-                    const R j2 = R(j2u - j2off);
-                    const R d0 = cd.x + j2 * h2x, d1 = cd.y + j2 * h2y, d2 = cd.z + j2 * h2z;
-                    const R fs = rns * gv, fp = rnp * gv;
-                    cs.x += fs * x.x;
-                    cs.y += fs * x.y;
-                    const R f0 = fp * d0, f1 = fp * d1, f2 = fp * d2;
-                    cp[0].x += f0 * x.x; cp[0].y += f0 * x.y;
-                    cp[1].x += f1 * x.x; cp[1].y += f1 * x.y;
-                    cp[2].x += f2 * x.x; cp[2].y += f2 * x.y;
-                    // Q_ij, i <= j: 00 11 22 01 02 12
-                    qq[0].x += f0 * d0 * x.x; qq[0].y += f0 * d0 * x.y;
-                    qq[1].x += f1 * d1 * x.x; qq[1].y += f1 * d1 * x.y;
-                    qq[2].x += f2 * d2 * x.x; qq[2].y += f2 * d2 * x.y;
-                    qq[3].x += f0 * d1 * x.x; qq[3].y += f0 * d1 * x.y;
-                    qq[4].x += f0 * d2 * x.x; qq[4].y += f0 * d2 * x.y;
-                    qq[5].x += f1 * d2 * x.x; qq[5].y += f1 * d2 * x.y;
-                }
-                // totals of the 20 moment components, four per register (row r of g[i]
-                // holds component 4 i + r), then read out of the rows' first lanes
-                const double g0 = totals4_wide(cs.x, cs.y, cp[0].x, cp[0].y);
-                const double g1 = totals4_wide(cp[1].x, cp[1].y, cp[2].x, cp[2].y);
-                const double g2 = totals4_wide(qq[0].x, qq[0].y, qq[1].x, qq[1].y);
-                const double g3 = totals4_wide(qq[2].x, qq[2].y, qq[3].x, qq[3].y);
-                const double g4 = totals4_wide(qq[4].x, qq[4].y, qq[5].x, qq[5].y);
-                double2 tcs, tcp[3], tqq[6];
-                tcs.x = readlane_d(g0, 0);
-                tcs.y = readlane_d(g0, 16);
-                tcp[0].x = readlane_d(g0, 32);
-                tcp[0].y = readlane_d(g0, 48);
-                tcp[1].x = readlane_d(g1, 0);
-                tcp[1].y = readlane_d(g1, 16);
-                tcp[2].x = readlane_d(g1, 32);
-                tcp[2].y = readlane_d(g1, 48);
-                tqq[0].x = readlane_d(g2, 0);
-                tqq[0].y = readlane_d(g2, 16);
-                tqq[1].x = readlane_d(g2, 32);
-                tqq[1].y = readlane_d(g2, 48);
-                tqq[2].x = readlane_d(g3, 0);
-                tqq[2].y = readlane_d(g3, 16);
-                tqq[3].x = readlane_d(g3, 32);
-                tqq[3].y = readlane_d(g3, 48);
-                tqq[4].x = readlane_d(g4, 0);
-                tqq[4].y = readlane_d(g4, 16);
-                tqq[5].x = readlane_d(g4, 32);
-                tqq[5].y = readlane_d(g4, 48);
-                const double Es = par[0], Ep = par[1];
-                const int qi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+                for (int i = 0; i < 6; ++i) { m2[i].x = R(0); m2[i].y = R(0); }
+                for (int ci = lane; ci < cnt; ci += 64) {
+                    const uint32_t cp = chunk_pack[c0 + ci];
+                    const Q4 g4 = gld4(chunk_g + c0 + ci);
+                    const int p0 = int(cp & 8191u), j2u0 = int((cp >> 13) & 127u), col = int(cp >> 20);
+                    const R gg[4] = {g4.x, g4.y, g4.z, g4.w};
+                    C y0, y1, y2;
+                    y0.x = R(0); y0.y = R(0); y1.x = R(0); y1.y = R(0); y2.x = R(0); y2.y = R(0);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    // s channel: c_{d_j,s} = (N_s/N_p) c_{p,j}
-                    double v = Es * (ns / np) * (tcp[j].x * tcs.y - tcp[j].y * tcs.x);
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) {
-                        const double2 qv = tqq[qi[i][j]];
-                        v += Ep * (qv.x * tcp[i].y - qv.y * tcp[i].x);
+                    for (int i = 0; i < 4; ++i) {
+                        C x = cmul(t2e[j2u0 + i], W[p0 + plane * i]);
+                        x.x *= gg[i];
+                        x.y *= gg[i];
+                        y0.x += x.x;
+                        y0.y += x.y;
+                        if (i > 0) {
+                            y1.x += R(i) * x.x;
+                            y1.y += R(i) * x.y;
+                            y2.x += R(i * i) * x.x;
+                            y2.y += R(i * i) * x.y;
+                        }
                     }
-                    jnl[j] += 2.0 * dV * dV * v;
+                    const C ph = cole[col];
+                    const Q4 cd = cold[col];
+                    const C X0 = cmul(ph, y0), X1 = cmul(ph, y1), X2 = cmul(ph, y2);
+                    const R j20 = R(j2u0 - j2off);
+                    const R d0[3] = {cd.x + j20 * h2x, cd.y + j20 * h2y, cd.z + j20 * h2z};
+                    m0.x += X0.x;
+                    m0.y += X0.y;
+#pragma unroll
+                    for (int a2 = 0; a2 < 3; ++a2) {
+                        m1[a2].x += d0[a2] * X0.x + hh[a2] * X1.x;
+                        m1[a2].y += d0[a2] * X0.y + hh[a2] * X1.y;
+                    }
+                    const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        const int i = pa[q], k = pb[q];
+                        const R f0 = d0[i] * d0[k], f1 = d0[i] * hh[k] + d0[k] * hh[i], f2 = hh[i] * hh[k];
+                        m2[q].x += f0 * X0.x + f1 * X1.x + f2 * X2.x;
+                        m2[q].y += f0 * X0.y + f1 * X1.y + f2 * X2.y;
+                    }
                 }
+                // totals of the 20 components, four per register: row r of g[i] holds component
+                // 4 i + r; the rows' first lanes store them
+                double g[5];
+                g[0] = totals4_wide(m0.x, m0.y, m1[0].x, m1[0].y);
+                g[1] = totals4_wide(m1[1].x, m1[1].y, m1[2].x, m1[2].y);
+                g[2] = totals4_wide(m2[0].x, m2[0].y, m2[1].x, m2[1].y);
+                g[3] = totals4_wide(m2[2].x, m2[2].y, m2[3].x, m2[3].y);
+                g[4] = totals4_wide(m2[4].x, m2[4].y, m2[5].x, m2[5].y);
+                if ((lane & 15) == 0) {
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) nlm[20 * t + 4 * i + (lane >> 4)] = g[i];
+                }
+            }
+            if (nat > 0) {
+                fo_prev = fo;
+                nl_pending = true;
             }
             // wave totals of the kinetic sums; each wave adds its share of this band's
             // current into its own FP64 slot (a fixed order, no atomics)
@@ -925,7 +970,7 @@ void k_propagate(PropArgs a) {
                 for (int q = 0; q < 3; ++q) {
                     const double kin = dV * (I.c[0][q] * qt[0] + I.c[1][q] * qt[1] + I.c[2][q] * qt[2]);
                     const double keq = kcart[3 * k + q] + Am[3 + q];
-                    wacc[4 * wave + q] += fo * (kin + keq * nrm + jnl[q]);
+                    wacc[4 * wave + q] += fo * (kin + keq * nrm);
                 }
             }
         }
@@ -939,6 +984,10 @@ void k_propagate(PropArgs a) {
             if (TDKS_ZOK(z)) rp[pr + plane * z] = RHO[pr + plane * z];
     }
     __syncthreads();
+    if (nl_pending) {  // the last band's split non-local current
+        nl_combine();
+        __syncthreads();
+    }
     if (tid < 3) {
         double s = 0.0;
         for (int w = 0; w < NW; ++w) s += wacc[4 * w + tid];
