@@ -36,16 +36,14 @@ struct DevInst {
     int ncol;                  // column images
     const int *col_atom;       // [ncol] atom of each column image
     const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8 | (r + 128) << 16
-    const uint32_t *ent_pack;  // atom-major entries: p | (j2 - r + N3 + 3) << 13 | col << 20
-    const float *ent_gf;       // radial factor g(|d|) of each entry, FP32 copy
-    const double *ent_gd;      // ... FP64 copy
+    // entries (support points of the column images), point-major: each packs
+    // p | (j2 - r + N3 + 3) << 13 | col << 20, with its radial factor g(|d|)
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
     const uint16_t *pt_ptr16;  // same, 16-bit copy (staged into LDS by the FP32 kernel)
     int nent;                  // projector entries
-    const uint32_t *pt_pack;   // point-major copy of ent_pack
-    const float *pt_gf;
-    const double *pt_gd;
-    const int *atom_ent;       // [nat+1] first atom-major entry of each atom
+    const uint32_t *pt_pack;   // [nent] packed entries
+    const float *pt_gf;        // [nent] radial factors, FP32 copy
+    const double *pt_gd;       // [nent] ... FP64 copy
     // chunks: up to 4 consecutive support points of one column image (consecutive j2,
     // no periodic wrap inside), packed like entries (first point); radial factors
     // g of the 4 points, zero-padded

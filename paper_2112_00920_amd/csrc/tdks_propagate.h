@@ -295,9 +295,6 @@ template <typename Q> __device__ __forceinline__ Q gld4(const Q *p) {
     return r;
 }
 
-template <typename R> __device__ __forceinline__ const R *gtab(const DevInst &I);
-template <> __device__ __forceinline__ const float *gtab<float>(const DevInst &I) { return I.ent_gf; }
-template <> __device__ __forceinline__ const double *gtab<double>(const DevInst &I) { return I.ent_gd; }
 template <typename R> __device__ __forceinline__ const R *chunktab(const DevInst &I);
 template <> __device__ __forceinline__ const float *chunktab<float>(const DevInst &I) { return I.chunk_gf; }
 template <> __device__ __forceinline__ const double *chunktab<double>(const DevInst &I) { return I.chunk_gd; }
@@ -373,9 +370,7 @@ void k_propagate(PropArgs a) {
     const bool rho_lds = sizeof(R) == 4 && a.rho_lds != 0;  // the FP64 kernels keep it in HBM
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
-    const auto *gt = gview(gtab<R>(I));
     const auto *pgt = gview(ptgtab<R>(I));
-    const auto *ent_pack = gview(I.ent_pack);
     const auto *chunk_pack = gview(I.chunk_pack);
     const Q4 *chunk_g = reinterpret_cast<const Q4 *>(chunktab<R>(I));
     const auto *pt_ptr = gview(I.pt_ptr);

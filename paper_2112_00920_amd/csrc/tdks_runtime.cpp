@@ -46,10 +46,10 @@ int fail(int code, const char *fmt, ...) {
 
 struct TableSet {
     std::vector<int> col_atom, col_j01;
-    std::vector<uint32_t> ent_pack, pt_pack;
-    std::vector<double> ent_g, pt_g;
-    std::vector<float> ent_gf, pt_gf;
-    std::vector<int> pt_ptr, atom_task, atom_ent;  // atom_ent: [nat+1] first entry of each atom
+    std::vector<uint32_t> pt_pack;
+    std::vector<double> pt_g;
+    std::vector<float> pt_gf;
+    std::vector<int> pt_ptr, atom_task;
     std::vector<uint32_t> chunk_pack;
     std::vector<double> chunk_g;   // [nchunk][4]
     std::vector<float> chunk_gf;
@@ -61,10 +61,10 @@ struct TableSet {
     int cls = -1;
     // device copies
     int *d_col_atom = nullptr, *d_col_j01 = nullptr;
-    uint32_t *d_ent_pack = nullptr, *d_pt_pack = nullptr;
-    double *d_ent_g = nullptr, *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
-    float *d_ent_gf = nullptr, *d_pt_gf = nullptr;
-    int *d_pt_ptr = nullptr, *d_atom_task = nullptr, *d_atom_ent = nullptr;
+    uint32_t *d_pt_pack = nullptr;
+    double *d_pt_g = nullptr, *d_atom_tau = nullptr, *d_atom_par = nullptr;
+    float *d_pt_gf = nullptr;
+    int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
     uint16_t *d_pt_ptr16 = nullptr;
     uint32_t *d_chunk_pack = nullptr;
     double *d_chunk_g = nullptr;
@@ -265,12 +265,10 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     std::vector<Ent> ents;
     T.col_atom.clear();
     T.col_j01.clear();
-    T.atom_ent.assign(nat + 1, 0);
     T.chunk_pack.clear();
     T.chunk_g.clear();
     T.atom_chunk.clear();
     for (int a = 0; a < nat; ++a) {
-        T.atom_ent[a] = int(ents.size());
         const tdks_species &sp = d.species[d.atom_species[a]];
         if (!(sp.Rc > 0.0) || !(sp.rc > 0.0)) return fail(TDKS_E_ARG, "species radii must be positive");
         const double gcut = std::exp(-sp.Rc * sp.Rc / (2.0 * sp.rc * sp.rc));
@@ -381,18 +379,13 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                                                  const std::pair<long long, Ent> &y) { return x.first < y.first; });
         for (auto &o : order) ents.push_back(o.second);
     }
-    T.atom_ent[nat] = int(ents.size());
     T.atom_chunk.push_back(int(T.chunk_pack.size()));
     T.chunk_gf.assign(T.chunk_g.begin(), T.chunk_g.end());
     if (T.col_atom.size() >= 4096)
         return fail(TDKS_E_UNSUPPORTED, "%zu projector column images exceed 4095", T.col_atom.size());
     std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
-    T.ent_pack.clear();
-    T.ent_g.clear();
     for (const Ent &e : ents) {
         const uint32_t pack = uint32_t(e.p) | (uint32_t(e.j2u) << 13) | (uint32_t(e.col) << 20);
-        T.ent_pack.push_back(pack);
-        T.ent_g.push_back(e.g);
         per_point[e.p].push_back({pack, e.g});
     }
     T.pt_ptr.assign(I.ng + 1, 0);
@@ -408,7 +401,6 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     T.pt_ptr[I.ng] = int(T.pt_pack.size());
     if (T.pt_pack.size() > 65535) return fail(TDKS_E_UNSUPPORTED, "more than 65535 projector entries");
     T.pt_ptr16.assign(T.pt_ptr.begin(), T.pt_ptr.end());
-    T.ent_gf.assign(T.ent_g.begin(), T.ent_g.end());
     T.pt_gf.assign(T.pt_g.begin(), T.pt_g.end());
     return TDKS_OK;
 }
@@ -748,7 +740,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         }
         S.ng_max = std::max(S.ng_max, I.ng);
         S.ncol_max = std::max(S.ncol_max, int(T.col_atom.size()));
-        S.nent_max = std::max(S.nent_max, int(T.ent_pack.size()));
+        S.nent_max = std::max(S.nent_max, int(T.pt_pack.size()));
         S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
         S.plane_max = std::max(S.plane_max, I.N[0] * I.N[1]);
         S.nat_max = std::max(S.nat_max, T.nat);
@@ -806,9 +798,6 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     for (TableSet &T : c->tables) {
         CHK(upload(c, &T.d_col_atom, T.col_atom));
         CHK(upload(c, &T.d_col_j01, T.col_j01));
-        CHK(upload(c, &T.d_ent_pack, T.ent_pack));
-        CHK(upload(c, &T.d_ent_g, T.ent_g));
-        CHK(upload(c, &T.d_ent_gf, T.ent_gf));
         CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
         CHK(upload(c, &T.d_pt_ptr16, T.pt_ptr16));
         CHK(upload(c, &T.d_pt_pack, T.pt_pack));
@@ -816,7 +805,6 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         CHK(upload(c, &T.d_pt_gf, T.pt_gf));
         CHK(upload(c, &T.d_task, T.task));
         CHK(upload(c, &T.d_atom_task, T.atom_task));
-        CHK(upload(c, &T.d_atom_ent, T.atom_ent));
         CHK(upload(c, &T.d_chunk_pack, T.chunk_pack));
         CHK(upload(c, &T.d_chunk_g, T.chunk_g));
         CHK(upload(c, &T.d_chunk_gf, T.chunk_gf));
@@ -881,18 +869,14 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.ncol = int(T.col_atom.size());
         D.col_atom = T.d_col_atom;
         D.col_j01 = T.d_col_j01;
-        D.ent_pack = T.d_ent_pack;
-        D.ent_gf = T.d_ent_gf;
-        D.ent_gd = T.d_ent_g;
         D.pt_ptr = T.d_pt_ptr;
         D.pt_ptr16 = T.d_pt_ptr16;
-        D.nent = int(T.ent_pack.size());
+        D.nent = int(T.pt_pack.size());
         D.pt_pack = T.d_pt_pack;
         D.pt_gf = T.d_pt_gf;
         D.pt_gd = T.d_pt_g;
         D.task = T.d_task;
         D.atom_task = T.d_atom_task;
-        D.atom_ent = T.d_atom_ent;
         D.chunk_pack = T.d_chunk_pack;
         D.chunk_gf = T.d_chunk_gf;
         D.chunk_gd = T.d_chunk_g;
