@@ -798,7 +798,10 @@ void k_propagate(PropArgs a) {
                             if (TDKS_ZOK(z)) gst(out + pw + plane * z, hz[z]);
                     }
                 } else {
-                    const R cm = R(a.dt / m);
+                    // dt/m through a reciprocal of the (wave-uniform) order: one multiply
+                    // instead of a double-precision division per thread
+                    const double rm = (m == 1) ? 1.0 : (m == 2) ? 0.5 : (m == 3) ? (1.0 / 3.0) : 0.25;
+                    const R cm = R(a.dt * rm);
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
                         C wn;  // (-i dt/m) h w
