@@ -48,7 +48,14 @@ def uniform_shift_fraction(m: int, j: int) -> Fraction:
 
 
 def kset(kspec):
-    """Fractional k-points of one instance from its KSpec."""
+    """Fractional k-points of one instance from its KSpec: Eq. (10) with the shift
+    (q, p, r) taken from a uniform shift grid, a Halton point (Sec. II.B) or given."""
+    if getattr(kspec, "halton_index", None) is not None:
+        m = int(kspec.halton_index)
+        q = [radical_inverse(m, b) for b in (2, 3, 5)]
+        return monkhorst_pack(kspec.coarse, q)
+    if getattr(kspec, "shift_q", None) is not None:
+        return monkhorst_pack(kspec.coarse, list(kspec.shift_q))
     if kspec.shifts is None:
         return monkhorst_pack(kspec.coarse)
     q = [uniform_shift(kspec.shifts[d], kspec.shift_index[d]) for d in range(3)]

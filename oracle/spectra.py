@@ -58,3 +58,24 @@ def standard_error(samples):
     s = np.asarray(samples)
     n = s.shape[0]
     return np.std(s, axis=0, ddof=1) / np.sqrt(n)
+
+
+def nh_convergence(t, samples, k0, omega, n_values, gamma=0.005):
+    """Two-step average over the first N_H shifts for each N_H in n_values (Sec. III.A):
+    per N_H the dielectric function of the mean delta J (Eqs. (12)-(14)), and the standard
+    error of its real and imaginary parts over the N_H per-shift results.  samples is
+    [N_H, n_t] (one field direction)."""
+    out = []
+    for n in n_values:
+        dj_mean = np.zeros(len(t))
+        for m in range(n):
+            dj_mean = dj_mean + np.asarray(samples[m], float)
+        dj_mean = dj_mean / n
+        eps = dielectric(conductivity(t, dj_mean, k0, omega, gamma), omega)
+        per = np.array([dielectric(conductivity(t, samples[m], k0, omega, gamma), omega) for m in range(n)])
+        if n > 1:
+            sem = standard_error(per.real) + 1j * standard_error(per.imag)
+        else:
+            sem = np.zeros(len(omega), dtype=complex)
+        out.append((n, eps, sem))
+    return out

@@ -98,6 +98,11 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"libtdks.so not found at {path}; build it with "
                           "`python -m paper_2112_00920_amd.build`")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7); importing
+    # torch first makes this library bind to that one, so that a process holds one HIP
+    # runtime whose device memory and streams both sides share
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     for name, (res, args) in SYMBOLS.items():
         fn = getattr(lib, name)

@@ -39,7 +39,22 @@ def shifted_grid(coarse, shifts, index) -> np.ndarray:
 
 
 def from_spec(kspec) -> np.ndarray:
-    if kspec.shifts is None:
+    """k-points of one sub-simulation: the coarse MP grid shifted by a uniform-grid shift,
+    a Halton point or an explicit shift (Eq. (10))."""
+    given = [kspec.shifts is not None, getattr(kspec, "halton_index", None) is not None,
+             getattr(kspec, "shift_q", None) is not None]
+    if sum(given) > 1:
+        raise ValueError("give at most one of shifts, halton_index, shift_q")
+    if given[1]:
+        if int(kspec.halton_index) < 1:
+            raise ValueError("halton_index counts from 1")
+        return mp_grid(kspec.coarse, halton_shifts(1, start=int(kspec.halton_index))[0])
+    if given[2]:
+        q = np.asarray(kspec.shift_q, float)
+        if q.shape != (3,) or np.any(q < 0.0) or np.any(q >= 1.0):
+            raise ValueError("shift_q must be three numbers in [0, 1)")
+        return mp_grid(kspec.coarse, q)
+    if not given[0]:
         return mp_grid(kspec.coarse)
     return shifted_grid(kspec.coarse, kspec.shifts, kspec.shift_index)
 

@@ -46,3 +46,35 @@ def test_spectra_match_oracle():
                                rtol=1e-10, atol=1e-30)
     m, sem = ps.group_mean_and_sem(np.stack([dj, 2 * dj, 3 * dj]))
     np.testing.assert_allclose(sem, osp.standard_error(np.stack([dj, 2 * dj, 3 * dj])), rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["twostep_g16_mp8_halton64", "twostep_g16_mp8_random64"])
+def test_halton_and_random_shift_ksets_bit_exact(name):
+    for inst in W.config(name).instances:
+        assert np.array_equal(pk.from_spec(inst.kspec), ok.kset(inst.kspec))
+
+
+def test_kspec_errors():
+    with pytest.raises(ValueError):
+        pk.from_spec(W.KSpec((2, 2, 2), (2, 2, 2), (0, 0, 0), halton_index=3))
+    with pytest.raises(ValueError):
+        pk.from_spec(W.KSpec((2, 2, 2), halton_index=0))
+    with pytest.raises(ValueError):
+        pk.from_spec(W.KSpec((2, 2, 2), shift_q=(0.5, 1.0, 0.2)))
+
+
+def test_nh_convergence_matches_oracle():
+    rng = np.random.default_rng(3)
+    t = np.arange(0, 100.0, 0.02)
+    dj = rng.standard_normal((9, len(t), 3)) * 1e-5
+    om = np.linspace(0.05, 1.0, 15)
+    rows = ps.nh_convergence(t, dj, 1e-3, om, axis=1)
+    assert [r["n_h"] for r in rows] == [1, 2, 4, 8, 9]
+    ref = osp.nh_convergence(t, dj[:, :, 1], 1e-3, om, [1, 2, 4, 8, 9])
+    for r, (n, eps, sem) in zip(rows, ref):
+        assert r["n_h"] == n
+        np.testing.assert_allclose(r["eps"], eps, rtol=1e-12)
+        np.testing.assert_allclose(r["eps_sem"].real, sem.real, rtol=1e-10, atol=1e-15)
+        np.testing.assert_allclose(r["eps_sem"].imag, sem.imag, rtol=1e-10, atol=1e-15)
+        np.testing.assert_allclose(r["dj_mean"], dj[:n, :, 1].mean(axis=0), rtol=1e-12)
+    assert rows[-1]["dev"] == 0.0

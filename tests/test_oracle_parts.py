@@ -203,3 +203,47 @@ def test_hhg_window_and_peak():
 def test_standard_error():
     x = np.array([[1.0], [2.0], [3.0], [4.0]])
     assert abs(spectra.standard_error(x)[0] - np.std([1, 2, 3, 4], ddof=1) / 2) < 1e-15
+
+
+@pytest.mark.parametrize("axis,base,N", [(0, 2, 3), (1, 3, 2), (2, 5, 4)])
+def test_halton_two_step_average_closed_form(axis, base, N):
+    """Two-step average (Eq. (9)) of f(k) = cos(2 pi N k_d) over Halton-shifted MP grids
+    (Eq. (10), Sec. II.B).  On every shifted grid f = (-1)^(N+1) cos(2 pi q_m) (the
+    N-point grid aliases this frequency), and the radical inverses of m = 0..B^j - 1 are
+    the points i / B^j, whose cosines sum to 0; without m = 0 the sum over
+    m = 1..B^j - 1 is -1.  So the average over N_H = B^j - 1 shifts is
+    (-1)^N / (B^j - 1)."""
+    coarse = [1, 1, 1]
+    coarse[axis] = N
+    for j in (1, 2):
+        n_h = base ** j - 1
+        tot = 0.0
+        for m in range(1, n_h + 1):
+            k = kpoints.kset(W.KSpec(tuple(coarse), halton_index=m))
+            tot += np.mean(np.cos(2 * np.pi * N * k[:, axis]))
+        assert abs(tot / n_h - (-1) ** N / n_h) < 1e-12
+
+
+def test_explicit_shift_is_eq10():
+    q = (0.3, 0.05, 0.9)
+    k = kpoints.kset(W.KSpec((2, 3, 1), shift_q=q))
+    ref = [[(2 * n1 - 3 + 2 * q[0]) / 4, (2 * n2 - 4 + 2 * q[1]) / 6, (2 - 2 + 2 * q[2]) / 2]
+           for n2 in (1, 2, 3) for n1 in (1, 2)]
+    np.testing.assert_allclose(k, kpoints.wrap_half(ref), rtol=0, atol=1e-15)
+
+
+def test_nh_convergence_scaled_copies():
+    """delta J_m = c_m g(t): eps is affine in delta J, so eps(N_H) - 1 = mean(c_1..c_N)
+    (eps_g - 1) and the standard error of its real and imaginary parts is
+    std(c_1..c_N) / sqrt(N) |Re, Im (eps_g - 1)|."""
+    t = np.arange(0.0, 100.0, 0.05)
+    g = 1e-5 * np.exp(-0.01 * t) * np.sin(0.3 * t)
+    c = np.array([1.0, 3.0, -2.0, 0.5, 4.0, 2.5])
+    om = np.linspace(0.1, 1.0, 7)
+    eg = spectra.dielectric(spectra.conductivity(t, g, 1e-3, om), om) - 1.0
+    rows = spectra.nh_convergence(t, c[:, None] * g[None, :], 1e-3, om, [1, 2, 6])
+    for n, eps, sem in rows:
+        np.testing.assert_allclose(eps - 1.0, c[:n].mean() * eg, rtol=1e-11, atol=1e-14)
+        s = c[:n].std(ddof=1) / np.sqrt(n) if n > 1 else 0.0
+        np.testing.assert_allclose(sem.real, s * np.abs(eg.real), rtol=1e-10, atol=1e-14)
+        np.testing.assert_allclose(sem.imag, s * np.abs(eg.imag), rtol=1e-10, atol=1e-14)

@@ -96,14 +96,21 @@ class KSpec:
     """k-sampling specification (not the k-points themselves).
 
     coarse: Monkhorst-Pack divisions (N1, N2, N3) of Eq. (8).
-    shifts: number of uniform shifts per axis (M1, M2, M3) of the second
-            sampling, or None for a plain MP grid.
-    shift_index: which shift (j1, j2, j3), 0 <= j_d < M_d, this sub-grid uses.
+    The second sampling's shift (q, p, r) of Eq. (10) is given by at most one of:
+    shifts, shift_index: a uniform shift grid, (M1, M2, M3) shifts per axis, and
+            which one (j1, j2, j3), 0 <= j_d < M_d, this sub-grid uses;
+    halton_index: the index m >= 1 of a Halton point in bases 2, 3, 5 (the
+            paper's choice, Sec. II.B); each side generates the point itself;
+    shift_q: an explicit shift in [0, 1)^3, e.g. seeded random numbers drawn
+            here (random shifts give a true standard error, Sec. III.A).
+    With none of them the sub-grid is the plain MP grid.
     """
 
     coarse: Tuple[int, int, int]
     shifts: Optional[Tuple[int, int, int]] = None
     shift_index: Optional[Tuple[int, int, int]] = None
+    halton_index: Optional[int] = None
+    shift_q: Optional[Tuple[float, float, float]] = None
 
 
 @dataclass
@@ -211,11 +218,15 @@ def config(name: str) -> Workload:
     diamond8_g12_mp2:     plain method, 8-atom cell on 12^3, 16 bands, 2^3 MP, kick, 500 steps.
     diamond8_g16_mp8:     plain method, 16^3, 16 bands, 8^3 MP (512 k), kick, 4000 steps.
     twostep_g16_mp8_s4:   two-step, 8^3 coarse x 4^3 uniform shifts = 64 sub-simulations, 16^3.
+    twostep_g16_mp8_halton64: the same with the shifts of the first 64 Halton points (the
+                          paper's choice, Sec. II.B).
+    twostep_g16_mp8_random64: the same with 64 seeded uniform random shifts.
     hhg_twostep_g20_mp4_s4: two-step HHG, 4^3 coarse x 4^3 shifts, 20^3, sin^2 pulse.
     uneven40:             40 uneven instances (fcc2 / diamond8 16^3 or 20^3 / super16).
     """
     seeds = {"diamond8_g12_mp2": 1, "diamond8_g16_mp8": 2, "twostep_g16_mp8_s4": 3,
-             "hhg_twostep_g20_mp4_s4": 4, "uneven40": 5}
+             "hhg_twostep_g20_mp4_s4": 4, "uneven40": 5, "twostep_g16_mp8_halton64": 3,
+             "twostep_g16_mp8_random64": 3}
     seed = seeds[name]
     rng = np.random.default_rng(seed)
     sp = draw_species(rng)
@@ -232,6 +243,18 @@ def config(name: str) -> Workload:
                 for j1 in range(4):
                     inst.append(make_instance("diamond8", (16, 16, 16), 16, [sp],
                                               KSpec((8, 8, 8), (4, 4, 4), (j1, j2, j3))))
+        return Workload(name, inst, 0.02, 4000, Field("kick", 1e-3), "scf", seed)
+    if name in ("twostep_g16_mp8_halton64", "twostep_g16_mp8_random64"):
+        # same species draw as the uniform-shift workload (same seed); the random shifts come
+        # from a generator of their own so that the species stay identical
+        qrng = np.random.default_rng(1000 + seed)
+        inst = []
+        for m in range(1, 65):
+            if name.endswith("halton64"):
+                ks = KSpec((8, 8, 8), halton_index=m)
+            else:
+                ks = KSpec((8, 8, 8), shift_q=tuple(float(x) for x in qrng.random(3)))
+            inst.append(make_instance("diamond8", (16, 16, 16), 16, [sp], ks))
         return Workload(name, inst, 0.02, 4000, Field("kick", 1e-3), "scf", seed)
     if name == "hhg_twostep_g20_mp4_s4":
         e_peak = float(rng.uniform(0.01, 0.03))
