@@ -176,6 +176,34 @@ int tdks_step(tdks_ctx *ctx, int n_steps, const double *A_tab);
 /* Number of steps recorded since the last load (a load resets the record). */
 int tdks_steps_done(tdks_ctx *ctx);
 
+/* Ground-state preparation (the runs of Sec. III start from the Kohn-Sham
+ * ground state; delta J is measured against it).  Starting from the loaded
+ * (or present) orbitals of every instance, runs n_iter iterations of:
+ *   1. the propagator of Eq. (1) at imaginary time, exp(-tau h_k) with A = 0,
+ *      by the same Taylor-4 expansion and kernels as tdks_step
+ *      (w_m = (-tau/m) h w_{m-1}), filtering the bands towards the lowest
+ *      eigenvectors of h_k;
+ *   2. Cholesky orthonormalisation of the bands of each k (S = U^H U dV =
+ *      L L^H, U <- U L^{-H}, FP64);
+ *   3. the density rho_out (Eq. 3) and the residual sum |rho_out - rho_in| dV;
+ *   4. SCF mode: linear mixing rho_in <- (1 - mix) rho_in + mix rho_out and
+ *      v_Hxc[rho_in]; FROZEN / NONE modes keep their potential (rho_in <-
+ *      rho_out).
+ * rho_in starts as the density of the starting orbitals.  With every band
+ * occupied, rho, J and the total energy depend only on the span of the bands,
+ * which converges to the lowest n_bands eigenvectors when h_k has a gap above
+ * them.  Afterwards rho, v_Hxc and J_pre are those of the final orbitals (as
+ * after tdks_load_orbitals) and the step counter is reset.  residual (HOST
+ * [n_inst], may be NULL) receives the last iteration's residual per instance.
+ * n_iter = 0 only recomputes rho, v_Hxc and J_pre.  Synchronises.
+ * Stability: the Taylor-4 filter is bounded for tau lambda_max(h_k) < 2.78; the
+ * call rejects tau whose kinetic bound alone exceeds 2.5 / tau.
+ * Errors: E_ARG (n_iter < 0, tau <= 0 or too large, mix outside (0, 1]),
+ * E_STATE (an instance not loaded), E_UNSUPPORTED (more than 32 bands),
+ * E_NUMERIC (linearly dependent bands: S not positive definite; orbitals of
+ * that k are left unchanged), E_OOM, E_HIP. */
+int tdks_ground_state(tdks_ctx *ctx, int n_iter, double tau, double mix, double *residual);
+
 /* Copies the induced current delta J^n = J^n - J_pre for n = 1..steps_done
  * into out (HOST).  mode TDKS_PER_INSTANCE: [n_inst][steps][3];
  * TDKS_PER_GROUP: [n_groups][steps][3], the plain mean over the instances of

@@ -187,6 +187,13 @@ class Propagator:
         A = np.ascontiguousarray(A_tab, dtype=np.float64).reshape(-1, 2, 3)
         _lib.check(self._lib.tdks_step(self._ctx, len(A), _ptr(A)))
 
+    def ground_state(self, n_iter: int, tau: float, mix: float = 0.5) -> np.ndarray:
+        """Imaginary-time ground-state preparation of every instance (tdks_ground_state);
+        returns the last iteration's density residual per instance."""
+        res = np.zeros(self.n_inst)
+        _lib.check(self._lib.tdks_ground_state(self._ctx, int(n_iter), float(tau), float(mix), _ptr(res)))
+        return res
+
     @property
     def steps_done(self) -> int:
         return int(self._lib.tdks_steps_done(self._ctx))

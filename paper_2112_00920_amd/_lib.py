@@ -72,6 +72,8 @@ SYMBOLS = {
     "tdks_load_orbitals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "tdks_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p]),
     "tdks_steps_done": (ctypes.c_int, [ctypes.c_void_p]),
+    "tdks_ground_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_void_p]),
     "tdks_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, ctypes.c_size_t,
                                     ctypes.POINTER(ctypes.c_size_t)]),
     "tdks_current_pre": (ctypes.c_int, [ctypes.c_void_p, c_double_p]),

@@ -22,6 +22,10 @@ SOURCES = [
     "tdks_prop_f32_nonorth.hip",
     "tdks_prop_f64_orth.hip",
     "tdks_prop_f64_nonorth.hip",
+    "tdks_itime_f32_orth.hip",
+    "tdks_itime_f32_nonorth.hip",
+    "tdks_itime_f64_orth.hip",
+    "tdks_itime_f64_nonorth.hip",
     "tdks_kernels.hip",
     "tdks_runtime.cpp",
 ]
@@ -30,7 +34,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("TDKS_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-    # packed FP32 instructions stay off (hardware notes)
+    # packed FP32 instructions stay off: some of their forms have produced wrong results,
+    # without an error, on the MI355X machines this was developed on
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]

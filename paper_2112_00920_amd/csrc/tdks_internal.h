@@ -76,7 +76,12 @@ struct WorkItem {
 #define TDKS_PROPAGATE_RAGGED_CONFIGS(X) \
     X(4, 512, 4) X(4, 1024, 4) X(8, 512, 2) X(8, 1024, 4) X(10, 1024, 4)
 
-enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2 };
+// STEP: real-time Taylor-4 step + density/current partials; OBSERVE: partials only;
+// APPLY: one h application; ITIME: imaginary-time Taylor-4 step exp(-tau h) (dt holds tau),
+// orbitals stored, no partials
+enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3 };
+
+constexpr int kOrthMaxBands = 32;  // bands per k the orthonormalisation kernel holds in LDS
 
 struct PropArgs {
     const DevInst *insts;
@@ -113,5 +118,8 @@ hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
 hipError_t launch_convert_in(const double *src, void *dst, size_t n_complex, int fp64, hipStream_t s);
 hipError_t launch_convert_out(const void *src, double *dst, size_t n_complex, int fp64, hipStream_t s);
 hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, double *out, hipStream_t s);
+hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int fp64, int *status, hipStream_t s);
+hipError_t launch_mix(const DevInst *insts, int n_inst, int ng_max, double *rho, double *rho_in, double alpha,
+                      double *resid, hipStream_t s);
 
 }  // namespace tdks

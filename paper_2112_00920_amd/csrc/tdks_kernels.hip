@@ -8,6 +8,10 @@ hipError_t launch_propagate_f32_orth(const PropArgs &, int, int, int, int, int, 
 hipError_t launch_propagate_f32_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
 hipError_t launch_propagate_f64_orth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
 hipError_t launch_propagate_f64_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_itime_f32_orth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_itime_f32_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_itime_f64_orth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
+hipError_t launch_itime_f64_nonorth(const PropArgs &, int, int, int, int, int, int, hipStream_t);
 
 size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block) {
     return propagate_lds_bytes_inl(fp64, sl, a, block);
@@ -28,6 +32,12 @@ bool propagate_config_ok(int block, int zl, int minw, int ragged) {
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
                             int nonorth, int sl, int ragged, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (a.mode == MODE_ITIME) {
+        if (fp64) return nonorth ? launch_itime_f64_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
+                                 : launch_itime_f64_orth(a, n_items, block, zl, minw, sl, ragged, s);
+        return nonorth ? launch_itime_f32_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
+                       : launch_itime_f32_orth(a, n_items, block, zl, minw, sl, ragged, s);
+    }
     if (fp64) return nonorth ? launch_propagate_f64_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
                              : launch_propagate_f64_orth(a, n_items, block, zl, minw, sl, ragged, s);
     return nonorth ? launch_propagate_f32_nonorth(a, n_items, block, zl, minw, sl, ragged, s)
@@ -311,6 +321,185 @@ hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, d
     else
         hipLaunchKernelGGL(k_norms<float2>, dim3(n_orb), dim3(256), 0, s,
                            reinterpret_cast<const float2 *>(u), ng, dV, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Ground-state preparation: Cholesky orthonormalisation of the bands of one k-point,
+// S = U^H U dV = L L^H, U <- U L^{-H} (the first band keeps its direction).  One
+// workgroup per (instance, k); FP64 throughout, orbitals read twice and written once.
+// Each Gram entry is summed by one thread in point order, so results are reproducible.
+constexpr int kOrthTile = 32;  // grid points per LDS tile
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
+    constexpr int NB = kOrthMaxBands, TP = kOrthTile;
+    __shared__ double2 S[NB * NB];         // Gram matrix, then L (lower triangle)
+    __shared__ double2 Li[NB * NB];        // L^{-1} (lower triangle)
+    __shared__ double2 T[NB * (TP + 1)];   // tile [band][point], padded rows
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int2 pr = pairs[blockIdx.x];
+    const DevInst &I = insts[pr.x];
+    const int nb = I.nb, ng = I.ng;
+    C *u = reinterpret_cast<C *>(I.u) + size_t(pr.y) * nb * ng;
+    const int ne = nb * nb;
+    double2 acc[(NB * NB) / 256];
+#pragma unroll
+    for (int q = 0; q < (NB * NB) / 256; ++q) acc[q] = make_double2(0.0, 0.0);
+    if (tid == 0) bad = 0;
+    // ---- Gram matrix over tiles of points
+    for (int p0 = 0; p0 < ng; p0 += TP) {
+        const int np = (ng - p0 < TP) ? ng - p0 : TP;
+        __syncthreads();  // previous tile consumed
+        for (int idx = tid; idx < nb * TP; idx += 256) {
+            const int b = idx / TP, pp = idx - b * TP;
+            double2 v = make_double2(0.0, 0.0);
+            if (pp < np) {
+                const C x = u[size_t(b) * ng + p0 + pp];
+                v = make_double2(double(x.x), double(x.y));
+            }
+            T[b * (TP + 1) + pp] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (NB * NB) / 256; ++q) {
+            const int e = tid + 256 * q;
+            if (e < ne) {
+                const int i = e / nb, j = e - i * nb;
+                const double2 *ti = T + i * (TP + 1), *tj = T + j * (TP + 1);
+                double sr = acc[q].x, si = acc[q].y;
+                for (int pp = 0; pp < np; ++pp) {  // conj(u_i) u_j
+                    const double2 a = ti[pp], b = tj[pp];
+                    sr += a.x * b.x + a.y * b.y;
+                    si += a.x * b.y - a.y * b.x;
+                }
+                acc[q] = make_double2(sr, si);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (NB * NB) / 256; ++q) {
+        const int e = tid + 256 * q;
+        if (e < ne) S[e] = make_double2(acc[q].x * I.dV, acc[q].y * I.dV);
+    }
+    __syncthreads();
+    // ---- Cholesky S = L L^H in place, one column per round (rows in parallel)
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            double d = S[j * nb + j].x;
+            for (int k = 0; k < j; ++k) {
+                const double2 l = S[j * nb + k];
+                d -= l.x * l.x + l.y * l.y;
+            }
+            if (!(d > 0.0)) {
+                bad = 1;
+                d = 1.0;
+            }
+            S[j * nb + j] = make_double2(sqrt(d), 0.0);
+        }
+        __syncthreads();
+        if (tid > j && tid < nb) {
+            double2 v = S[tid * nb + j];
+            for (int k = 0; k < j; ++k) {  // - L_ik conj(L_jk)
+                const double2 a = S[tid * nb + k], b = S[j * nb + k];
+                v.x -= a.x * b.x + a.y * b.y;
+                v.y -= a.y * b.x - a.x * b.y;
+            }
+            const double r = 1.0 / S[j * nb + j].x;
+            S[tid * nb + j] = make_double2(v.x * r, v.y * r);
+        }
+        __syncthreads();
+    }
+    if (bad) {  // S not positive definite: the bands are linearly dependent
+        if (tid == 0) status[0] = 1;
+        return;
+    }
+    // ---- L^{-1}, one column per thread: Li_cc = 1 / L_cc, Li_ic = -(sum_{c<=k<i} L_ik Li_kc) / L_ii
+    if (tid < nb) {
+        const int c = tid;
+        for (int i = 0; i < nb; ++i) Li[i * nb + c] = make_double2(0.0, 0.0);
+        Li[c * nb + c] = make_double2(1.0 / S[c * nb + c].x, 0.0);
+        for (int i = c + 1; i < nb; ++i) {
+            double2 v = make_double2(0.0, 0.0);
+            for (int k = c; k < i; ++k) {
+                const double2 a = S[i * nb + k], b = Li[k * nb + c];
+                v.x += a.x * b.x - a.y * b.y;
+                v.y += a.x * b.y + a.y * b.x;
+            }
+            const double r = -1.0 / S[i * nb + i].x;
+            Li[i * nb + c] = make_double2(v.x * r, v.y * r);
+        }
+    }
+    // ---- U <- U L^{-H}: u_new_b(p) = sum_{i<=b} u_i(p) conj(Li_bi), tile by tile
+    for (int p0 = 0; p0 < ng; p0 += TP) {
+        const int np = (ng - p0 < TP) ? ng - p0 : TP;
+        __syncthreads();  // Li ready / previous tile written
+        for (int idx = tid; idx < nb * TP; idx += 256) {
+            const int b = idx / TP, pp = idx - b * TP;
+            double2 v = make_double2(0.0, 0.0);
+            if (pp < np) {
+                const C x = u[size_t(b) * ng + p0 + pp];
+                v = make_double2(double(x.x), double(x.y));
+            }
+            T[b * (TP + 1) + pp] = v;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nb * TP; idx += 256) {
+            const int b = idx / TP, pp = idx - b * TP;
+            if (pp >= np) continue;
+            double xr = 0.0, xi = 0.0;
+            for (int i = 0; i <= b; ++i) {
+                const double2 a = T[i * (TP + 1) + pp], l = Li[b * nb + i];
+                xr += a.x * l.x + a.y * l.y;  // a conj(l)
+                xi += a.y * l.x - a.x * l.y;
+            }
+            C out;
+            out.x = decltype(out.x)(xr);
+            out.y = decltype(out.y)(xi);
+            u[size_t(b) * ng + p0 + pp] = out;
+        }
+    }
+}
+
+hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int fp64, int *status,
+                       hipStream_t s) {
+    if (n_pairs <= 0) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_orth<double2>, dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+    else
+        hipLaunchKernelGGL(k_orth<float2>, dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+    return hipGetLastError();
+}
+
+// Linear density mixing of the ground-state iteration, one workgroup per instance:
+// resid = sum |rho_out - rho_in| dV, rho_in <- (1 - alpha) rho_in + alpha rho_out, and the
+// mixed density replaces rho_out (v_Hxc is built from it next).
+__global__ __launch_bounds__(256) void k_mix(const DevInst *insts, int ng_max, double *rho, double *rho_in,
+                                             double alpha, double *resid) {
+    __shared__ double red[4];
+    const int inst = blockIdx.x;
+    const DevInst &I = insts[inst];
+    double *ro = rho + size_t(inst) * ng_max;
+    double *ri = rho_in + size_t(inst) * ng_max;
+    double s = 0.0;
+    for (int p = threadIdx.x; p < I.ng; p += 256) {
+        const double o = ro[p], i = ri[p];
+        s += fabs(o - i);
+        const double m = (1.0 - alpha) * i + alpha * o;
+        ri[p] = m;
+        ro[p] = m;
+    }
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) resid[inst] = (red[0] + red[1] + red[2] + red[3]) * I.dV;
+}
+
+hipError_t launch_mix(const DevInst *insts, int n_inst, int ng_max, double *rho, double *rho_in, double alpha,
+                      double *resid, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mix, dim3(n_inst), dim3(256), 0, s, insts, ng_max, rho, rho_in, alpha, resid);
     return hipGetLastError();
 }
 

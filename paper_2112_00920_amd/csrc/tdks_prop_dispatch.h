@@ -1,0 +1,49 @@
+// Dispatch of the k_propagate instantiations of one translation unit.  The including
+// file defines REAL (float / double), NONORTH_FLAG, ITIME_FLAG (imaginary-time variant)
+// and LAUNCH_NAME; the split lets the variants compile in parallel.
+#pragma once
+#include "tdks_propagate.h"
+
+namespace tdks {
+
+template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED>
+static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    auto kern = k_propagate<REAL, ZL, NONORTH_FLAG, MAXT, MINW, SL, RAGGED, ITIME_FLAG>;
+    const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, SL, a, block);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(block), lds, s, a);
+    return hipGetLastError();
+}
+
+// the imaginary-time variants read the projector tables from global memory only (no
+// LDS-staged copy), which halves their instantiations; SL is a speed choice, not a result
+template <bool IT>
+static hipError_t dispatch(const PropArgs &a, int n_items, int block, int zl, int minw, int sl, int ragged,
+                           hipStream_t s) {
+#define TDKS_CASE(Z, M, O, RG)                                                                      \
+    if (ragged == RG && zl == Z && block <= M && minw == O) {                                       \
+        if constexpr (IT) {                                                                         \
+            return launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                             \
+        } else {                                                                                    \
+            return sl ? launch_zl<Z, M, O, true, RG>(a, n_items, block, s)                          \
+                      : launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                        \
+        }                                                                                           \
+    }
+#define TDKS_CASE_EVEN(Z, M, O) TDKS_CASE(Z, M, O, false)
+#define TDKS_CASE_RAGGED(Z, M, O) TDKS_CASE(Z, M, O, true)
+    TDKS_PROPAGATE_CONFIGS(TDKS_CASE_EVEN)
+    TDKS_PROPAGATE_RAGGED_CONFIGS(TDKS_CASE_RAGGED)
+#undef TDKS_CASE_RAGGED
+#undef TDKS_CASE_EVEN
+#undef TDKS_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t LAUNCH_NAME(const PropArgs &a, int n_items, int block, int zl, int minw, int sl, int ragged,
+                       hipStream_t s) {
+    return dispatch<ITIME_FLAG>(a, n_items, block, zl, minw, sl, ragged, s);
+}
+
+}  // namespace tdks

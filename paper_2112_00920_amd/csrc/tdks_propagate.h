@@ -327,7 +327,7 @@ __device__ __forceinline__ void nl_current(const double *m, double Es, double Ep
     }
 }
 
-template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL, bool RAGGED>
+template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -460,7 +460,7 @@ void k_propagate(PropArgs a) {
     cx[0] = uni(R(-I.g[0][1]));  // -(1/2) * 2 g_de for d < e
     cx[1] = uni(R(-I.g[0][2]));
     cx[2] = uni(R(-I.g[1][2]));
-    const int norder = (a.mode == MODE_STEP) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
+    const int norder = (a.mode == MODE_STEP || ITIME) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
     // non-local current of a band: its per-task moment totals are combined per atom (in task
     // order) after the next barrier, with the band's weight kept in fo_prev
     double fo_prev = 0.0;
@@ -804,9 +804,14 @@ void k_propagate(PropArgs a) {
                     const R cm = R(a.dt * rm);
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
-                        C wn;  // (-i dt/m) h w
-                        wn.x = cm * hz[z].y;
-                        wn.y = -cm * hz[z].x;
+                        C wn;  // (-i dt/m) h w, or (-tau/m) h w in imaginary time (dt holds tau)
+                        if (ITIME) {
+                            wn.x = -cm * hz[z].x;
+                            wn.y = -cm * hz[z].y;
+                        } else {
+                            wn.x = cm * hz[z].y;
+                            wn.y = -cm * hz[z].x;
+                        }
                         acc[z].x += wn.x;
                         acc[z].y += wn.y;
                         wc[z] = wn;
@@ -829,7 +834,7 @@ void k_propagate(PropArgs a) {
                     if (!TDKS_ZOK(z)) continue;
                     const int p = ps + plane * z;
                     W[p] = acc[z];
-                    if (a.mode == MODE_STEP) gst(ug + p, acc[z]);
+                    if (a.mode == MODE_STEP || ITIME) gst(ug + p, acc[z]);
                     const double ux = double(acc[z].x), uy = double(acc[z].y);
                     const double r = fo * (ux * ux + uy * uy);
                     if (rho_lds)
@@ -838,6 +843,7 @@ void k_propagate(PropArgs a) {
                         rp[p] = first ? r : rp[p] + r;
                 }
             }
+            if (ITIME) continue;  // imaginary time: the filtered orbital only
             __syncthreads();
             // per-thread sums over the owned points in the orbital precision, FP64 beyond.
             // Summed over the whole periodic grid, sum_p Im(conj(u_p) (u_{p+s} - u_{p-s}))
@@ -973,7 +979,7 @@ void k_propagate(PropArgs a) {
             }
         }
     }
-    if (a.mode == MODE_APPLY) return;
+    if (a.mode == MODE_APPLY || ITIME) return;
     if (rho_lds && active) {
         auto *rp = gview_w(I.rho_part + size_t(w_slot) * ng);
         const int pr = opq(pbase + plane * z0);

@@ -127,6 +127,12 @@ struct tdks_ctx {
     int *d_ctrs = nullptr;  // [0] A row, [1] record index, [2] always 0
     double *d_jpre = nullptr, *d_jobs = nullptr, *d_Aobs = nullptr;
     std::vector<double> jpre;
+    // ground-state preparation (allocated on first use): input density of the mixing,
+    // residual per instance, (instance, k) list of the orthonormalisation, status flag
+    double *d_rho_in = nullptr, *d_resid = nullptr;
+    int2 *d_pairs = nullptr;
+    int n_pairs = 0;
+    int *d_status = nullptr;
     int steps_done = 0;
     hipGraphExec_t g_chunk = nullptr, g_one = nullptr;
     int chunk = 16;
@@ -596,10 +602,9 @@ size_t orb_bytes(const tdks_ctx *c, const InstHost &I) {
     return size_t(I.nk) * I.nb * I.ng * (c->fp64 ? 16 : 8);
 }
 
-// observe: current (and density) of instance range for given A; writes d_jobs or d_jpre
-int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jdst) {
-    double h[6] = {A[0], A[1], A[2], A[0], A[1], A[2]};
-    HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+// observe: current (and density) of instance range for given A; writes d_jobs or d_jpre.
+// enqueue_observe leaves the work on the stream; d_Aobs must already hold A.
+int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst) {
     for (const ShapeClass &S : c->classes) {
         int wb = S.wend, we = S.wbeg;
         for (int i = i_first; i <= i_last; ++i) {
@@ -616,8 +621,37 @@ int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jds
     }
     HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
                          c->stream));
+    return TDKS_OK;
+}
+
+int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jdst) {
+    double h[6] = {A[0], A[1], A[2], A[0], A[1], A[2]};
+    HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    CHK(enqueue_observe(c, i_first, i_last, jdst));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TDKS_OK;
+}
+
+// Upper bound of the kinetic part of h_k over the instance's k-set: per axis the 4th-order
+// second difference reaches 16/3 at the zone edge, the first difference at most
+// max |8 sin t - sin 2t| / 6 < 1.3722; |k|^2 / 2 on top.
+double kinetic_bound(const InstHost &I) {
+    const double s1 = 1.3722;
+    double b = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        b += 0.5 * (16.0 / 3.0) * I.g[d][d];
+        for (int e = 0; e < 3; ++e)
+            if (e != d) b += 0.5 * std::fabs(I.g[d][e]) * s1 * s1;
+    }
+    double kmax = 0.0;
+    for (int k = 0; k < I.nk; ++k) {
+        const double *kc = &I.kcart[3 * k];
+        double t = 0.5 * (kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]);
+        for (int d = 0; d < 3; ++d)
+            t += std::fabs(kc[0] * I.c[d][0] + kc[1] * I.c[d][1] + kc[2] * I.c[d][2]) * s1;
+        kmax = std::max(kmax, t);
+    }
+    return b + kmax;
 }
 
 }  // namespace
@@ -997,6 +1031,78 @@ int tdks_step(tdks_ctx *c, int n_steps, const double *A_tab) {
 }
 
 int tdks_steps_done(tdks_ctx *c) { return c ? c->steps_done : 0; }
+
+int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *residual) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    if (n_iter < 0) return fail(TDKS_E_ARG, "n_iter < 0");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(TDKS_E_ARG, "tau must be positive and finite");
+    if (!(mix > 0.0 && mix <= 1.0)) return fail(TDKS_E_ARG, "mix must lie in (0, 1]");
+    for (int i = 0; i < c->n_inst; ++i) {
+        const InstHost &I = c->inst[i];
+        if (!I.loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+        if (I.nb > kOrthMaxBands)
+            return fail(TDKS_E_UNSUPPORTED, "instance %d: %d bands; the orthonormalisation holds at most %d",
+                        i, I.nb, kOrthMaxBands);
+        const double lam = kinetic_bound(I);
+        if (tau * lam > 2.5)
+            return fail(TDKS_E_ARG, "instance %d: tau %.4g too large for the Taylor-4 filter (kinetic bound %.4g Ha;"
+                        " need tau * bound <= 2.5)", i, tau, lam);
+    }
+    CHK(sync_in(c));
+    if (!c->d_pairs) {
+        std::vector<int2> pairs;
+        for (int i = 0; i < c->n_inst; ++i)
+            for (int k = 0; k < c->inst[i].nk; ++k) pairs.push_back(make_int2(i, k));
+        CHK(upload(c, &c->d_pairs, pairs));
+        c->n_pairs = int(pairs.size());
+        c->d_rho_in = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_inst));
+        c->d_resid = static_cast<double *>(c->alloc(sizeof(double) * c->n_inst));
+        c->d_status = static_cast<int *>(c->alloc(sizeof(int)));
+        if (!c->d_rho_in || !c->d_resid || !c->d_status) return fail(TDKS_E_OOM, "ground-state buffers");
+    }
+    const bool scf = (c->opt.hxc_mode == TDKS_HXC_SCF);
+    const double zero6[6] = {0, 0, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(c->d_Aobs, zero6, sizeof(zero6), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
+    HIPCHK(launch_fill_int(c->d_status, 0, 1, c->stream));
+    HIPCHK(hipMemsetAsync(c->d_resid, 0, sizeof(double) * c->n_inst, c->stream));
+    // the mixing starts from the density of the current orbitals (what v_Hxc was built from)
+    HIPCHK(hipMemcpyAsync(c->d_rho_in, c->d_rho, sizeof(double) * size_t(c->ng_max) * c->n_inst,
+                          hipMemcpyDeviceToDevice, c->stream));
+    for (int it = 0; it < n_iter; ++it) {
+        for (const ShapeClass &S : c->classes) {
+            PropArgs a = class_args(c, S, MODE_ITIME, c->d_Aobs, c->d_ctrs + 2);
+            a.dt = tau;
+            a.work = c->d_work + S.wbeg;
+            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
+                                    c->stream));
+        }
+        HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, c->fp64, c->d_status, c->stream));
+        CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jobs));
+        HIPCHK(launch_mix(c->d_insts, c->n_inst, c->ng_max, c->d_rho, c->d_rho_in, scf ? mix : 1.0, c->d_resid,
+                          c->stream));
+        if (scf)
+            HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot,
+                              c->fp64, c->stream));
+    }
+    // the prepared state: density, v_Hxc and the current before the field of the final orbitals
+    CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jpre));
+    if (scf)
+        HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64,
+                          c->stream));
+    int status = 0;
+    HIPCHK(hipMemcpyAsync(c->jpre.data(), c->d_jpre, sizeof(double) * 3 * c->n_inst, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(&status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    if (residual)
+        HIPCHK(hipMemcpyAsync(residual, c->d_resid, sizeof(double) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->steps_done = 0;
+    CHK(sync_out(c));
+    if (status) return fail(TDKS_E_NUMERIC, "orthonormalisation met linearly dependent bands");
+    return TDKS_OK;
+}
 
 int tdks_current(tdks_ctx *c, int mode, double *out, size_t cap, size_t *n_written) {
     if (!c || !out) return fail(TDKS_E_ARG, "null argument");
