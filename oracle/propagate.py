@@ -8,6 +8,14 @@ Step n -> n+1 (explicit 4th-order Taylor expansion of exp(-i h dt)):
   rho^{n+1} = rho(u^{n+1}); v_Hxc^{n+1} recomputed ('scf'), kept ('frozen'),
   or zero ('none');  J^{n+1} = J(u^{n+1}, kappa = k + A(t_{n+1})).
 
+Predictor-corrector variant ('pc', SCF only; the paper's Octopus runs leave the
+propagator to that code): the Hxc potential of the step is taken at the mid-step,
+  predictor  u~ = T4(h[v_n]) u^n, v~ = v_Hxc[rho(u~)],
+  corrector  u^{n+1} = T4(h[(v_n + v~) / 2]) u^n,
+which makes the coupling through v_Hxc second order in dt (the explicit step holds
+v_Hxc[rho(t_n)] over the whole step: first order).  With a frozen or zero
+potential both variants are the same step.
+
 Current (Eq. (5)) with the kinetic momentum pi = (1/i)[r, h] (Eq. (6)):
   J = -(1/Omega) sum_k w_k sum_b f_b [ sum_r u* (-i grad_FD + kappa) u dV
                                        + sum_{a,lm} 2 E_l Im(conj(c_d) c) ],
@@ -76,7 +84,10 @@ def norms(sys: System, u):
 class Run:
     """A single TDDFT simulation driven step by step."""
 
-    def __init__(self, sys: System, u0, dt, hxc_mode="scf", v_hxc_frozen=None):
+    def __init__(self, sys: System, u0, dt, hxc_mode="scf", v_hxc_frozen=None, propagator="taylor"):
+        if propagator not in ("taylor", "pc"):
+            raise ValueError(propagator)
+        self.propagator = propagator
         self.sys = sys
         self.u = np.array(u0, dtype=complex)
         self.dt = float(dt)
@@ -93,9 +104,17 @@ class Run:
 
     def step(self, A_mid, A_end):
         sys = self.sys
+        v = self.v_hxc
+        if self.propagator == "pc" and self.mode == "scf":
+            u_pred = np.empty_like(self.u)
+            for k in range(sys.nk):
+                kappa = sys.k_cart[k] + np.asarray(A_mid, float)
+                u_pred[k] = taylor_step(sys, kappa, self.v_hxc, self.u[k], self.dt)
+            v_pred = hxc_potential(sys.cell, density(sys, u_pred))
+            v = 0.5 * (self.v_hxc + v_pred)
         for k in range(sys.nk):
             kappa = sys.k_cart[k] + np.asarray(A_mid, float)
-            self.u[k] = taylor_step(sys, kappa, self.v_hxc, self.u[k], self.dt)
+            self.u[k] = taylor_step(sys, kappa, v, self.u[k], self.dt)
         if self.mode == "scf":
             self.v_hxc = hxc_potential(sys.cell, density(sys, self.u))
         return current(sys, A_end, self.u)
