@@ -72,6 +72,10 @@ extern "C" {
 #define TDKS_HXC_FROZEN 1 /* v_Hxc fixed to the array given in the descriptor    */
 #define TDKS_HXC_NONE 2   /* v_Hxc = 0                                           */
 
+/* propagators (tdks_options.propagator) */
+#define TDKS_PROP_TAYLOR 0 /* explicit Taylor-4 step, h with v_Hxc[rho(t_n)]      */
+#define TDKS_PROP_PC 1     /* predictor-corrector: v_Hxc at the mid-step (SCF)    */
+
 /* memory location flags */
 #define TDKS_HOST 0
 #define TDKS_DEVICE 1
@@ -128,6 +132,7 @@ typedef struct tdks_options {
     int graph_steps;      /* steps captured per HIP graph (0 = 16; <0 disables)    */
     int waves_per_simd;   /* occupancy target of the propagation kernel: 2 or 4
                              (0 = automatic); selects the register budget          */
+    int propagator;       /* TDKS_PROP_TAYLOR (default) or TDKS_PROP_PC            */
 } tdks_options;
 
 typedef struct tdks_ctx tdks_ctx;
@@ -166,7 +171,13 @@ int tdks_load_orbitals(tdks_ctx *ctx, int inst, const void *u, int where);
 
 /* Advances every instance by n_steps Taylor-4 steps (Eq. 1) under the uniform
  * vector potential table A_tab (HOST, [n_steps][2][3]: A(t_n + dt/2) used in
- * h for step n, and A(t_{n+1}) used for the current recorded after it).  The
+ * h for step n, and A(t_{n+1}) used for the current recorded after it).
+ * With TDKS_PROP_PC and SCF Hxc each step is a predictor-corrector pair: a
+ * predictor Taylor-4 step from u^n with v_Hxc[rho(t_n)] whose density gives
+ * v~ (its orbitals are not stored), then the step from u^n with
+ * (v_Hxc[rho(t_n)] + v~) / 2; twice the propagation work, and the Hxc coupling
+ * becomes second order in dt.  With frozen or no Hxc the two propagators are
+ * the same step.  The
  * current J^{n+1} (Eq. 5) of every instance is recorded after every step.
  * Enqueued asynchronously (HIP graphs of opt->graph_steps steps); the host
  * does no per-step work.  Errors: E_STATE (an instance not loaded), E_ARG,
@@ -248,8 +259,9 @@ int tdks_apply_h(tdks_ctx *ctx, int inst, const void *w, void *hw, const double 
  * step's kernels one by one (no graph) with HIP events recorded on the
  * context's stream around them, and returns the mean device time per step in
  * out (HOST [3], milliseconds): [0] the propagation kernels (Taylor-4 step with
- * density and current partials), [1] the reduction, Hxc and counter kernels,
- * [2] the whole step.  Synchronises.  Same errors as tdks_step. */
+ * density and current partials; predictor and corrector for TDKS_PROP_PC),
+ * [1] the reduction, Hxc, mid-step potential and counter kernels, [2] the
+ * whole step.  Synchronises.  Same errors as tdks_step. */
 int tdks_time_kernels(tdks_ctx *ctx, int n_steps, const double *A_tab, double *out);
 
 /* Tiling actually used by the first grid shape: threads per workgroup, length of

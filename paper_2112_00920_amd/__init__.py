@@ -73,7 +73,8 @@ class Propagator:
     def __init__(self, instances: Sequence, k_fracs: Optional[Sequence] = None, precision: str = "fp64",
                  dt: float = 0.02, hxc_mode: str = "scf", v_hxc_frozen: Optional[Sequence] = None,
                  bands_per_group: int = 0, k_per_group: int = 0, block_size: int = 0,
-                 graph_steps: int = 16, waves_per_simd: int = 0, use_torch: bool = True):
+                 graph_steps: int = 16, waves_per_simd: int = 0, use_torch: bool = True,
+                 propagator: str = "taylor"):
         self._lib = _lib.load()
         self._ctx = None
         self.n_inst = len(instances)
@@ -119,6 +120,7 @@ class Propagator:
         opt.k_per_group = int(k_per_group)
         opt.block_size = int(block_size)
         opt.graph_steps = int(graph_steps)
+        opt.propagator = {"taylor": _lib.PROP_TAYLOR, "pc": _lib.PROP_PC}[propagator]
         opt.waves_per_simd = int(waves_per_simd)
         self._alloc = None
         self._torch = None

@@ -11,6 +11,7 @@ TDKS_OK = 0
 E_ARG, E_OOM, E_HIP, E_STATE, E_NUMERIC, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 HXC_SCF, HXC_FROZEN, HXC_NONE = 0, 1, 2
+PROP_TAYLOR, PROP_PC = 0, 1
 HOST, DEVICE = 0, 1
 PER_INSTANCE, PER_GROUP = 0, 1
 
@@ -60,6 +61,7 @@ class Options(ctypes.Structure):
         ("block_size", ctypes.c_int),
         ("graph_steps", ctypes.c_int),
         ("waves_per_simd", ctypes.c_int),
+        ("propagator", ctypes.c_int),
     ]
 
 

@@ -78,8 +78,9 @@ struct WorkItem {
 
 // STEP: real-time Taylor-4 step + density/current partials; OBSERVE: partials only;
 // APPLY: one h application; ITIME: imaginary-time Taylor-4 step exp(-tau h) (dt holds tau),
-// orbitals stored, no partials
-enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3 };
+// orbitals stored, no partials; PREDICT: real-time step whose orbitals are not stored, density
+// partials only (the predictor of the predictor-corrector step)
+enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3, MODE_PREDICT = 4 };
 
 constexpr int kOrthMaxBands = 32;  // bands per k the orthonormalisation kernel holds in LDS
 
@@ -113,6 +114,8 @@ hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const 
                       const double *vloc, double *vhxc, void *vtot, int fp64, hipStream_t s);
 hipError_t launch_vtot(const DevInst *insts, int inst0, int n, int ng_max, const double *vloc,
                        const double *vhxc, void *vtot, int fp64, hipStream_t s);
+hipError_t launch_vmid(const DevInst *insts, int n, int ng_max, const double *vloc, const double *va,
+                       const double *vb, void *vtot, int fp64, hipStream_t s);
 hipError_t launch_advance(int *ctrs, int n, hipStream_t s);
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
 hipError_t launch_convert_in(const double *src, void *dst, size_t n_complex, int fp64, hipStream_t s);

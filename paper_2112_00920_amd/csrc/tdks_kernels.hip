@@ -236,6 +236,31 @@ hipError_t launch_vtot(const DevInst *insts, int inst0, int n, int ng_max, const
     return hipGetLastError();
 }
 
+// Mid-step potential of the predictor-corrector step: vtot = v_loc + (v_a + v_b) / 2.
+template <typename R>
+__global__ void k_vmid(const DevInst *insts, int ng_max, const double *vloc, const double *va,
+                       const double *vb, R *vtot) {
+    const int inst = blockIdx.y;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < insts[inst].ng) {
+        const size_t o = size_t(inst) * ng_max + p;
+        vtot[o] = R(vloc[o] + 0.5 * (va[o] + vb[o]));
+    }
+}
+
+hipError_t launch_vmid(const DevInst *insts, int n, int ng_max, const double *vloc, const double *va,
+                       const double *vb, void *vtot, int fp64, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((ng_max + 255) / 256, n);
+    if (fp64)
+        hipLaunchKernelGGL(k_vmid<double>, grid, dim3(256), 0, s, insts, ng_max, vloc, va, vb,
+                           reinterpret_cast<double *>(vtot));
+    else
+        hipLaunchKernelGGL(k_vmid<float>, grid, dim3(256), 0, s, insts, ng_max, vloc, va, vb,
+                           reinterpret_cast<float *>(vtot));
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // small utility kernels (graph-capturable: no memset nodes)
 __global__ void k_advance(int *ctrs, int n) {

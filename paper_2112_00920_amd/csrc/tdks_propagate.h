@@ -460,7 +460,7 @@ void k_propagate(PropArgs a) {
     cx[0] = uni(R(-I.g[0][1]));  // -(1/2) * 2 g_de for d < e
     cx[1] = uni(R(-I.g[0][2]));
     cx[2] = uni(R(-I.g[1][2]));
-    const int norder = (a.mode == MODE_STEP || ITIME) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
+    const int norder = (a.mode == MODE_STEP || a.mode == MODE_PREDICT || ITIME) ? 4 : (a.mode == MODE_APPLY ? 1 : 0);
     // non-local current of a band: its per-task moment totals are combined per atom (in task
     // order) after the next barrier, with the band's weight kept in fo_prev
     double fo_prev = 0.0;
@@ -843,7 +843,7 @@ void k_propagate(PropArgs a) {
                         rp[p] = first ? r : rp[p] + r;
                 }
             }
-            if (ITIME) continue;  // imaginary time: the filtered orbital only
+            if (ITIME || a.mode == MODE_PREDICT) continue;  // no current: imaginary time, predictor
             __syncthreads();
             // per-thread sums over the owned points in the orbital precision, FP64 beyond.
             // Summed over the whole periodic grid, sum_p Im(conj(u_p) (u_{p+s} - u_{p-s}))

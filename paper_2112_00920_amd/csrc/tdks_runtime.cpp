@@ -118,6 +118,7 @@ struct tdks_ctx {
     DevInst *d_insts = nullptr;
     WorkItem *d_work = nullptr;
     double *d_rho = nullptr, *d_vloc = nullptr, *d_vhxc = nullptr;
+    double *d_vhxc_pred = nullptr;  // predictor-corrector: v_Hxc of the predicted density
     void *d_vtot = nullptr;
     double *d_trace = nullptr;
     size_t trace_cap = 0;  // records per instance
@@ -524,14 +525,34 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     return a;
 }
 
-// enqueue one time step of every instance (graph-capturable)
-int enqueue_step(tdks_ctx *c) {
+// the propagation launches of one step of every instance (mode STEP or PREDICT)
+int enqueue_propagation(tdks_ctx *c, int mode) {
     for (const ShapeClass &S : c->classes) {
-        PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
+        PropArgs a = class_args(c, S, mode, c->d_A, c->d_ctrs);
         a.work = c->d_work + S.wbeg;
         HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
                                 c->stream));
     }
+    return TDKS_OK;
+}
+
+bool predictor_corrector(const tdks_ctx *c) {
+    return c->opt.propagator == TDKS_PROP_PC && c->opt.hxc_mode == TDKS_HXC_SCF;
+}
+
+// after the predictor: its density, v~ = v_Hxc[rho~] (kept apart), and the mid-step potential
+// v_loc + (v_Hxc[rho(t_n)] + v~) / 2 for the corrector; the predictor's current is discarded
+int enqueue_predictor_tail(tdks_ctx *c) {
+    HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_jobs, 1, nullptr, c->stream));
+    HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc_pred, c->d_vtot,
+                      c->fp64, c->stream));
+    HIPCHK(launch_vmid(c->d_insts, c->n_inst, c->ng_max, c->d_vloc, c->d_vhxc, c->d_vhxc_pred, c->d_vtot, c->fp64,
+                       c->stream));
+    return TDKS_OK;
+}
+
+// after the step: density and recorded current, v_Hxc[rho(t_{n+1})], counters
+int enqueue_step_tail(tdks_ctx *c) {
     HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
                          c->d_ctrs + 1, c->stream));
     if (c->opt.hxc_mode == TDKS_HXC_SCF)
@@ -539,6 +560,16 @@ int enqueue_step(tdks_ctx *c) {
                           c->fp64, c->stream));
     HIPCHK(launch_advance(c->d_ctrs, 2, c->stream));
     return TDKS_OK;
+}
+
+// enqueue one time step of every instance (graph-capturable)
+int enqueue_step(tdks_ctx *c) {
+    if (predictor_corrector(c)) {
+        CHK(enqueue_propagation(c, MODE_PREDICT));
+        CHK(enqueue_predictor_tail(c));
+    }
+    CHK(enqueue_propagation(c, MODE_STEP));
+    return enqueue_step_tail(c);
 }
 
 int build_graph(tdks_ctx *c, int nsteps, hipGraphExec_t *out) {
@@ -692,6 +723,8 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     if (!(opt->dt != 0.0) || !std::isfinite(opt->dt)) return fail(TDKS_E_ARG, "dt must be finite and non-zero");
     if (opt->hxc_mode < TDKS_HXC_SCF || opt->hxc_mode > TDKS_HXC_NONE)
         return fail(TDKS_E_ARG, "unknown hxc_mode %d", opt->hxc_mode);
+    if (opt->propagator != TDKS_PROP_TAYLOR && opt->propagator != TDKS_PROP_PC)
+        return fail(TDKS_E_ARG, "unknown propagator %d", opt->propagator);
     c->fp64 = opt->precision == TDKS_FP64;
     c->n_inst = n_inst;
     c->chunk = opt->graph_steps == 0 ? 16 : opt->graph_steps;
@@ -855,6 +888,8 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     }
     CHK(upload(c, &c->d_vloc, vloc_all));
     CHK(upload(c, &c->d_vhxc, vhxc_all));
+    if (opt->propagator == TDKS_PROP_PC && opt->hxc_mode == TDKS_HXC_SCF)
+        CHK(upload(c, &c->d_vhxc_pred, vhxc_all));
     c->d_rho = static_cast<double *>(c->alloc(sizeof(double) * ngm));
     c->d_vtot = c->alloc((c->fp64 ? 8 : 4) * ngm);
     c->d_ctrs = static_cast<int *>(c->alloc(sizeof(int) * 4));
@@ -1270,34 +1305,30 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
     HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
     HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
-    std::vector<hipEvent_t> ev(3 * n_steps);
+    // per step: [0] start, [1] after the predictor's propagation, [2] after its tail (PC only),
+    // [3] after the step's propagation, [4] end
+    std::vector<hipEvent_t> ev(5 * n_steps);
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    const bool pc = predictor_corrector(c);
     int rc = TDKS_OK;
     for (int s = 0; s < n_steps && rc == TDKS_OK; ++s) {
-        HIPCHK(hipEventRecord(ev[3 * s], c->stream));
-        for (const ShapeClass &S : c->classes) {
-            PropArgs a = class_args(c, S, MODE_STEP, c->d_A, c->d_ctrs);
-            a.work = c->d_work + S.wbeg;
-            HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
-                                c->stream));
-        }
-        HIPCHK(hipEventRecord(ev[3 * s + 1], c->stream));
-        HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
-                             c->d_ctrs + 1, c->stream));
-        if (c->opt.hxc_mode == TDKS_HXC_SCF)
-            HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot,
-                              c->fp64, c->stream));
-        HIPCHK(launch_advance(c->d_ctrs, 2, c->stream));
-        HIPCHK(hipEventRecord(ev[3 * s + 2], c->stream));
+        HIPCHK(hipEventRecord(ev[5 * s], c->stream));
+        if (pc) CHK(enqueue_propagation(c, MODE_PREDICT));
+        HIPCHK(hipEventRecord(ev[5 * s + 1], c->stream));
+        if (pc) CHK(enqueue_predictor_tail(c));
+        HIPCHK(hipEventRecord(ev[5 * s + 2], c->stream));
+        CHK(enqueue_propagation(c, MODE_STEP));
+        HIPCHK(hipEventRecord(ev[5 * s + 3], c->stream));
+        CHK(enqueue_step_tail(c));
+        HIPCHK(hipEventRecord(ev[5 * s + 4], c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     double tp = 0.0, tr = 0.0;
     for (int s = 0; s < n_steps; ++s) {
-        float a = 0.f, b = 0.f;
-        HIPCHK(hipEventElapsedTime(&a, ev[3 * s], ev[3 * s + 1]));
-        HIPCHK(hipEventElapsedTime(&b, ev[3 * s + 1], ev[3 * s + 2]));
-        tp += a;
-        tr += b;
+        float t[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int q = 0; q < 4; ++q) HIPCHK(hipEventElapsedTime(&t[q], ev[5 * s + q], ev[5 * s + q + 1]));
+        tp += t[0] + t[2];
+        tr += t[1] + t[3];
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     out[0] = tp / n_steps;
