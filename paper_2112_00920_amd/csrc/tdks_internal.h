@@ -79,8 +79,10 @@ struct WorkItem {
 // STEP: real-time Taylor-4 step + density/current partials; OBSERVE: partials only;
 // APPLY: one h application; ITIME: imaginary-time Taylor-4 step exp(-tau h) (dt holds tau),
 // orbitals stored, no partials; PREDICT: real-time step whose orbitals are not stored, density
-// partials only (the predictor of the predictor-corrector step)
-enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3, MODE_PREDICT = 4 };
+// partials only (the predictor of the predictor-corrector step); DENSITY: density partials of the
+// present orbitals only
+enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3, MODE_PREDICT = 4,
+                  MODE_DENSITY = 5 };
 
 constexpr int kOrthMaxBands = 32;  // bands per k the orthonormalisation kernel holds in LDS
 

@@ -354,45 +354,72 @@ hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, d
 // S = U^H U dV = L L^H, U <- U L^{-H} (the first band keeps its direction).  One
 // workgroup per (instance, k); FP64 throughout, orbitals read twice and written once.
 // Each Gram entry is summed by one thread in point order, so results are reproducible.
-constexpr int kOrthTile = 32;  // grid points per LDS tile
+// The orbitals stream through LDS in tiles of TP points of all bands (TP as large as
+// the tile buffer allows, so a tile is 8 elements per thread); the next tile is loaded
+// into registers while the current one is used.
+constexpr int kOrthTileCap = 2080;  // double2 slots of the tile buffer (nb (TP + 1) <= cap)
+constexpr int kOrthPer = 8;         // tile elements per thread (nb TP <= 2048)
 
 template <typename C>
-__global__ __launch_bounds__(256) void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
-    constexpr int NB = kOrthMaxBands, TP = kOrthTile;
-    __shared__ double2 S[NB * NB];         // Gram matrix, then L (lower triangle)
-    __shared__ double2 Li[NB * NB];        // L^{-1} (lower triangle)
-    __shared__ double2 T[NB * (TP + 1)];   // tile [band][point], padded rows
+__device__ __forceinline__ void orth_fetch(const C *u, int ng, int nb, int tp, int p0, C *pre) {
+#pragma unroll
+    for (int q = 0; q < kOrthPer; ++q) {
+        const int idx = threadIdx.x + 256 * q;
+        const int b = idx / tp, pp = idx - b * tp;
+        C x;
+        x.x = 0;
+        x.y = 0;
+        if (b < nb && p0 + pp < ng) x = u[size_t(b) * ng + p0 + pp];
+        pre[q] = x;
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ void orth_stage(const C *pre, int nb, int tp, double2 *T) {
+#pragma unroll
+    for (int q = 0; q < kOrthPer; ++q) {
+        const int idx = threadIdx.x + 256 * q;
+        const int b = idx / tp, pp = idx - b * tp;
+        if (b < nb) T[b * (tp + 1) + pp] = make_double2(double(pre[q].x), double(pre[q].y));
+    }
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
+    constexpr int NB = kOrthMaxBands;
+    static_assert(NB * NB <= kOrthTileCap, "the Gram matrix shares the tile buffer");
+    __shared__ double2 T[kOrthTileCap];  // tile [band][point], rows padded by one
+    __shared__ double2 Li[NB * NB];      // L^{-1} (lower triangle)
     __shared__ int bad;
+    double2 *S = T;  // Gram matrix, then L (lower triangle): lives between the two tile passes
     const int tid = threadIdx.x;
     const int2 pr = pairs[blockIdx.x];
     const DevInst &I = insts[pr.x];
     const int nb = I.nb, ng = I.ng;
     C *u = reinterpret_cast<C *>(I.u) + size_t(pr.y) * nb * ng;
+    int tp = 16;
+    while (tp < 512 && nb * 2 * tp <= 256 * kOrthPer && nb * (2 * tp + 1) <= kOrthTileCap) tp *= 2;
     const int ne = nb * nb;
     double2 acc[(NB * NB) / 256];
 #pragma unroll
     for (int q = 0; q < (NB * NB) / 256; ++q) acc[q] = make_double2(0.0, 0.0);
     if (tid == 0) bad = 0;
+    C pre[kOrthPer];
     // ---- Gram matrix over tiles of points
-    for (int p0 = 0; p0 < ng; p0 += TP) {
-        const int np = (ng - p0 < TP) ? ng - p0 : TP;
+    orth_fetch(u, ng, nb, tp, 0, pre);
+    for (int p0 = 0; p0 < ng; p0 += tp) {
+        const int np = (ng - p0 < tp) ? ng - p0 : tp;
         __syncthreads();  // previous tile consumed
-        for (int idx = tid; idx < nb * TP; idx += 256) {
-            const int b = idx / TP, pp = idx - b * TP;
-            double2 v = make_double2(0.0, 0.0);
-            if (pp < np) {
-                const C x = u[size_t(b) * ng + p0 + pp];
-                v = make_double2(double(x.x), double(x.y));
-            }
-            T[b * (TP + 1) + pp] = v;
-        }
+        orth_stage(pre, nb, tp, T);
         __syncthreads();
+        if (p0 + tp < ng) orth_fetch(u, ng, nb, tp, p0 + tp, pre);
 #pragma unroll
         for (int q = 0; q < (NB * NB) / 256; ++q) {
             const int e = tid + 256 * q;
             if (e < ne) {
                 const int i = e / nb, j = e - i * nb;
-                const double2 *ti = T + i * (TP + 1), *tj = T + j * (TP + 1);
+                const double2 *ti = T + i * (tp + 1), *tj = T + j * (tp + 1);
                 double sr = acc[q].x, si = acc[q].y;
                 for (int pp = 0; pp < np; ++pp) {  // conj(u_i) u_j
                     const double2 a = ti[pp], b = tj[pp];
@@ -403,6 +430,7 @@ __global__ __launch_bounds__(256) void k_orth(const DevInst *insts, const int2 *
             }
         }
     }
+    __syncthreads();  // last tile consumed before S overwrites it
 #pragma unroll
     for (int q = 0; q < (NB * NB) / 256; ++q) {
         const int e = tid + 256 * q;
@@ -456,26 +484,23 @@ __global__ __launch_bounds__(256) void k_orth(const DevInst *insts, const int2 *
             Li[i * nb + c] = make_double2(v.x * r, v.y * r);
         }
     }
-    // ---- U <- U L^{-H}: u_new_b(p) = sum_{i<=b} u_i(p) conj(Li_bi), tile by tile
-    for (int p0 = 0; p0 < ng; p0 += TP) {
-        const int np = (ng - p0 < TP) ? ng - p0 : TP;
-        __syncthreads();  // Li ready / previous tile written
-        for (int idx = tid; idx < nb * TP; idx += 256) {
-            const int b = idx / TP, pp = idx - b * TP;
-            double2 v = make_double2(0.0, 0.0);
-            if (pp < np) {
-                const C x = u[size_t(b) * ng + p0 + pp];
-                v = make_double2(double(x.x), double(x.y));
-            }
-            T[b * (TP + 1) + pp] = v;
-        }
+    // ---- U <- U L^{-H}: u_new_b(p) = sum_{i<=b} u_i(p) conj(Li_bi), tile by tile (a tile is
+    // written only after it was read into LDS; the prefetch reads the next, untouched tile)
+    orth_fetch(u, ng, nb, tp, 0, pre);
+    for (int p0 = 0; p0 < ng; p0 += tp) {
+        const int np = (ng - p0 < tp) ? ng - p0 : tp;
+        __syncthreads();  // Li ready / previous tile consumed
+        orth_stage(pre, nb, tp, T);
         __syncthreads();
-        for (int idx = tid; idx < nb * TP; idx += 256) {
-            const int b = idx / TP, pp = idx - b * TP;
-            if (pp >= np) continue;
+        if (p0 + tp < ng) orth_fetch(u, ng, nb, tp, p0 + tp, pre);
+#pragma unroll
+        for (int q = 0; q < kOrthPer; ++q) {
+            const int idx = tid + 256 * q;
+            const int b = idx / tp, pp = idx - b * tp;
+            if (b >= nb || pp >= np) continue;
             double xr = 0.0, xi = 0.0;
             for (int i = 0; i <= b; ++i) {
-                const double2 a = T[i * (TP + 1) + pp], l = Li[b * nb + i];
+                const double2 a = T[i * (tp + 1) + pp], l = Li[b * nb + i];
                 xr += a.x * l.x + a.y * l.y;  // a conj(l)
                 xi += a.y * l.x - a.x * l.y;
             }

@@ -843,7 +843,8 @@ void k_propagate(PropArgs a) {
                         rp[p] = first ? r : rp[p] + r;
                 }
             }
-            if (ITIME || a.mode == MODE_PREDICT) continue;  // no current: imaginary time, predictor
+            // no current: imaginary time, predictor, density only
+            if (ITIME || a.mode == MODE_PREDICT || a.mode == MODE_DENSITY) continue;
             __syncthreads();
             // per-thread sums over the owned points in the orbital precision, FP64 beyond.
             // Summed over the whole periodic grid, sum_p Im(conj(u_p) (u_{p+s} - u_{p-s}))

@@ -635,7 +635,7 @@ size_t orb_bytes(const tdks_ctx *c, const InstHost &I) {
 
 // observe: current (and density) of instance range for given A; writes d_jobs or d_jpre.
 // enqueue_observe leaves the work on the stream; d_Aobs must already hold A.
-int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst) {
+int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int mode = MODE_OBSERVE) {
     for (const ShapeClass &S : c->classes) {
         int wb = S.wend, we = S.wbeg;
         for (int i = i_first; i <= i_last; ++i) {
@@ -645,7 +645,7 @@ int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst) {
             we = std::max(we, I.wend);
         }
         if (we <= wb) continue;
-        PropArgs a = class_args(c, S, MODE_OBSERVE, c->d_Aobs, c->d_ctrs + 2);
+        PropArgs a = class_args(c, S, mode, c->d_Aobs, c->d_ctrs + 2);
         a.work = c->d_work + wb;
         HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
                                 c->stream));
@@ -1113,7 +1113,7 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
                                     c->stream));
         }
         HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, c->fp64, c->d_status, c->stream));
-        CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jobs));
+        CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jobs, MODE_DENSITY));
         HIPCHK(launch_mix(c->d_insts, c->n_inst, c->ng_max, c->d_rho, c->d_rho_in, scf ? mix : 1.0, c->d_resid,
                           c->stream));
         if (scf)
