@@ -37,7 +37,7 @@ struct DevInst {
     const int *col_atom;       // [ncol] atom of each column image
     const int *col_j01;        // [ncol] (j0 + N1) | (j1 + N2) << 8 | (r + 128) << 16
     // entries (support points of the column images), point-major: each packs
-    // p | (j2 - r + N3 + 3) << 13 | col << 20, with its radial factor g(|d|)
+    // col | (j2 - r + N3 + 3) << 16, with its radial factor g(|d|)
     const int *pt_ptr;         // [ng+1] CSR: entries touching each grid point
     const uint16_t *pt_ptr16;  // same, 16-bit copy (staged into LDS by the FP32 kernel)
     int nent;                  // projector entries

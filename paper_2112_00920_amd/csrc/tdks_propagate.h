@@ -184,17 +184,21 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 #define D2C1 (4.0 / 3.0)
 #define D2C2 (-1.0 / 12.0)
 
-// packed projector entry: grid index p | (j2 + N3 + 3) << 13 | column image << 20 (j2 counted
-// from the column image's reference step)
-__device__ __forceinline__ void ent_unpack(uint32_t v, int &p, int &j2u, int &col) {
-    p = int(v & 8191u);
-    j2u = int((v >> 13) & 127u);
-    col = int(v >> 20);
-}
+// scatter entry staged in LDS by the FP32 kernel: the byte offset of its column image's
+// coefficients (low half) and its stored a_3 step (bits 16-23), with the radial factor
+template <typename R> struct PtRec;
+template <> struct PtRec<float> {
+    uint32_t pk;
+    float g;
+};
+template <> struct PtRec<double> {
+    uint32_t pk, pad;
+    double g;
+};
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, nlm, ptp, ptk, ptg, rho, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, nlm, ptp, ptk, rho, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -223,8 +227,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.nlm = o; o = al16(o + 8 * 20 * size_t(ntask_max > 0 ? ntask_max : 1));  // current moments per task
     // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
-    L.ptk = o; o = al16(o + (sl ? 4 * size_t(nent_max) : 0));
-    L.ptg = o; o = al16(o + (sl ? r * size_t(nent_max) : 0));
+    L.ptk = o; o = al16(o + (sl ? (fp64 ? 16 : 8) * size_t(nent_max) : 0));  // PtRec records
     L.rho = o; o = al16(o + (rho_lds ? 8 * size_t(ng_max) : 0));  // FP64 density partial
     L.total = o;
     return L;
@@ -364,8 +367,7 @@ void k_propagate(PropArgs a) {
     double *wacc = reinterpret_cast<double *>(smem + L.wacc);  // current partial per wave (x, y, z, -)
     double *nlm = reinterpret_cast<double *>(smem + L.nlm);    // non-local current moments per task
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
-    uint32_t *ptk_l = reinterpret_cast<uint32_t *>(smem + L.ptk);
-    R *ptg_l = reinterpret_cast<R *>(smem + L.ptg);
+    PtRec<R> *ptk_l = reinterpret_cast<PtRec<R> *>(smem + L.ptk);
     double *RHO = reinterpret_cast<double *>(smem + L.rho);
     const bool rho_lds = sizeof(R) == 4 && a.rho_lds != 0;  // the FP64 kernels keep it in HBM
 
@@ -437,8 +439,11 @@ void k_propagate(PropArgs a) {
         const auto *p16 = gview(I.pt_ptr16);
         for (int i = tid; i <= ng; i += BS) ptp_l[i] = p16[i];
         for (int e = tid; e < I.nent; e += BS) {
-            ptk_l[e] = pt_pack[e];
-            ptg_l[e] = pgt[e];
+            const uint32_t pk = pt_pack[e];  // column image | stored a_3 step << 16
+            PtRec<R> rec;
+            rec.pk = (sizeof(R) == 4) ? ((pk & 0xffffu) * uint32_t(sizeof(Q4))) | (pk & 0xffff0000u) : pk;
+            rec.g = pgt[e];
+            ptk_l[e] = rec;
         }
     }
 
@@ -770,21 +775,35 @@ void k_propagate(PropArgs a) {
                             h.y += cx[q] * tot.y;
                         }
                     }
-                    // non-local part: projector entries touching p
-                    const int e0s = SL ? int(ptp_l[p]) : pt_ptr[p];
-                    const int e1 = SL ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
-                    for (int e = e0s; e < e1; ++e) {
-                        const uint32_t pk = SL ? ptk_l[e] : pt_pack[e];
-                        const int j2u = int((pk >> 13) & 127u), col = int(pk >> 20);
-                        const R gv = SL ? ptg_l[e] : pgt[e];
-                        const Q4 q = AB[col];
+                    // non-local part: projector entries touching p,
+                    //   h += g conj(t2(j2)) (A + j2 B) of the entry's column image
+                    auto scatter_one = [&](uint32_t pk, R gv, const Q4 &q) {
+                        const int j2u = int((pk >> 16) & 255u);
                         const C t2 = t2m[j2u];
                         const R j2 = R(j2u - j2off);
                         C s;
                         s.x = (q.x + j2 * q.z) * gv;
                         s.y = (q.y + j2 * q.w) * gv;
-                        h.x += t2.x * s.x + t2.y * s.y;  // conj(t2) * s
-                        h.y += t2.x * s.y - t2.y * s.x;
+                        h.x = fma(t2.x, s.x, h.x);  // h += conj(t2) * s
+                        h.x = fma(t2.y, s.y, h.x);
+                        h.y = fma(t2.x, s.y, h.y);
+                        h.y = fma(-t2.y, s.x, h.y);
+                    };
+                    if (SL) {  // LDS records; FP32 records hold the byte offset of the coefficients
+                        const PtRec<R> *r1 = ptk_l + int(ptp_l[p + 1]);
+                        for (const PtRec<R> *r = ptk_l + int(ptp_l[p]); r != r1; ++r) {
+                            const PtRec<R> rec = *r;
+                            const Q4 q = (sizeof(R) == 4)
+                                ? *reinterpret_cast<const Q4 *>(reinterpret_cast<const char *>(AB) + (rec.pk & 0xffffu))
+                                : AB[rec.pk & 0xffffu];
+                            scatter_one(rec.pk, rec.g, q);
+                        }
+                    } else {
+                        const int e1 = pt_ptr[p + 1];
+                        for (int e = pt_ptr[p]; e < e1; ++e) {
+                            const uint32_t pk = pt_pack[e];
+                            scatter_one(pk, pgt[e], AB[pk & 0xffffu]);
+                        }
                     }
                     hz[z] = h;
                 }

@@ -392,7 +392,7 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         return fail(TDKS_E_UNSUPPORTED, "%zu projector column images exceed 4095", T.col_atom.size());
     std::vector<std::vector<std::pair<uint32_t, double>>> per_point(I.ng);
     for (const Ent &e : ents) {
-        const uint32_t pack = uint32_t(e.p) | (uint32_t(e.j2u) << 13) | (uint32_t(e.col) << 20);
+        const uint32_t pack = uint32_t(e.col) | (uint32_t(e.j2u) << 16);  // scatter: column image, a_3 step
         per_point[e.p].push_back({pack, e.g});
     }
     T.pt_ptr.assign(I.ng + 1, 0);
