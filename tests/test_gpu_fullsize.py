@@ -147,3 +147,36 @@ def test_uneven_batch_full_size_sampled():
         first.setdefault((inst.cell, tuple(inst.grid)), i)
     _say(f"uneven40 kinds: {sorted(first.items())}")
     _sampled_parity("uneven40", sorted(first.values()), 1, 0.0)
+
+
+def test_ground_state_iteration_full_size_sampled():
+    """One imaginary-time iteration of the whole two-step workload in the benchmark's
+    configuration (FP32 orbitals): sampled k-points of one sub-simulation against the
+    oracle's imaginary-time step with the GPU's v_Hxc and its Cholesky orthonormalisation."""
+    import paper_2112_00920_amd as tdks
+    from oracle import ground as G
+
+    wl = W.config("twostep_g16_mp8_s4")
+    insts = wl.instances
+    inst_id, tau = 21, 0.1
+    _say("full-size ground-state iteration FP32: loading 64 sub-simulations")
+    with tdks.Propagator(insts, precision="fp32", dt=wl.dt) as prop:
+        u_keep = None
+        for i, inst in enumerate(insts):
+            u = W.random_orbitals_torch(3000 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+            prop.load_orbitals(i, u)
+            if i == inst_id:
+                u_keep = u.cpu().numpy()
+            del u
+        vh0 = prop.vhxc(inst_id)
+        res = prop.ground_state(1, tau, 0.5)
+        u1 = prop.get_orbitals(inst_id)
+    assert np.all(np.isfinite(res))
+    sysm = System(insts[inst_id])
+    u32 = u_keep.astype(np.complex64).astype(np.complex128)
+    rng = np.random.default_rng(7)
+    for k in rng.choice(512, 4, replace=False):
+        ref = G.orthonormalise(G.imaginary_time_step(sysm, sysm.k_cart[k], vh0, u32[k], tau), sysm.cell.dV)
+        err = np.max(np.abs(u1[k] - ref)) / np.max(np.abs(ref))
+        _say(f"  k {k}: orbital rel err {err:.2e}")
+        assert err < 2e-5
