@@ -92,3 +92,27 @@ def test_pulse_nonlinear_4000_steps():
     rel = np.abs(h32 - h64) / np.max(h64)
     _say(f"  harmonic power, |H32 - H64| / max H64 at orders 1..15: max {np.max(rel):.2e}")
     assert np.max(rel) < 1e-4
+
+
+def test_predictor_corrector_kick_4000_steps():
+    """The predictor-corrector propagator over the kick workload's length: FP32 against
+    FP64 (both predictor-corrector) on two two-step sub-simulations."""
+    import paper_2112_00920_amd as tdks
+
+    wl = W.config("twostep_g16_mp8_s4")
+    insts = [wl.instances[5], wl.instances[40]]
+    u0s = [W.random_orbitals_torch(700 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+           for i, inst in enumerate(insts)]
+    A = wl.field.table(N_STEPS, wl.dt)
+    _say(f"predictor-corrector kick: {len(insts)} sub-simulations, {N_STEPS} steps, FP32 then FP64")
+    out = {}
+    for prec in ("fp32", "fp64"):
+        with tdks.Propagator(insts, precision=prec, dt=wl.dt, propagator="pc") as prop:
+            for i, u in enumerate(u0s):
+                prop.load_orbitals(i, u)
+            prop.step(A)
+            out[prec] = prop.current(per="instance").mean(axis=0)
+    peak = np.max(np.abs(out["fp64"]))
+    err = np.max(np.abs(out["fp32"] - out["fp64"])) / peak
+    _say(f"  peak |dJ| {peak:.3e}; max |dJ32 - dJ64| / peak = {err:.2e}")
+    assert err < 1e-4

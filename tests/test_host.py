@@ -78,3 +78,19 @@ def test_nh_convergence_matches_oracle():
         np.testing.assert_allclose(r["eps_sem"].imag, sem.imag, rtol=1e-10, atol=1e-15)
         np.testing.assert_allclose(r["dj_mean"], dj[:n, :, 1].mean(axis=0), rtol=1e-12)
     assert rows[-1]["dev"] == 0.0
+
+
+def test_harness_table_rows():
+    from paper_2112_00920_amd import harness
+
+    rng = np.random.default_rng(11)
+    t = np.arange(1, 501) * 0.02
+    dj = rng.standard_normal((5, len(t), 3)) * 1e-5
+    om = np.linspace(0.1, 1.0, 9)
+    rows = harness.table(t, dj, 1e-3, om)
+    assert [r["n_h"] for r in rows] == [1, 2, 4, 5]
+    assert rows[0]["mean_sem_im_eps"] == 0.0 and rows[-1]["max_dev_eps"] == 0.0
+    full = ps.nh_convergence(t, dj, 1e-3, om)
+    for r, f in zip(rows, full):
+        assert r["max_dev_eps"] == f["dev"]
+        assert abs(r["max_sem_im_eps"] - float(np.max(f["eps_sem"].imag))) == 0.0
