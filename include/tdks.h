@@ -206,7 +206,8 @@ int tdks_steps_done(tdks_ctx *ctx);
  * them.  Afterwards rho, v_Hxc and J_pre are those of the final orbitals (as
  * after tdks_load_orbitals) and the step counter is reset.  residual (HOST
  * [n_inst], may be NULL) receives the last iteration's residual per instance.
- * n_iter = 0 only recomputes rho, v_Hxc and J_pre.  Synchronises.
+ * n_iter = 0 only recomputes rho, v_Hxc and J_pre (residual receives zeros).
+ * Synchronises.
  * Stability: the Taylor-4 filter is bounded for tau lambda_max(h_k) < 2.78; the
  * call rejects tau whose kinetic bound alone exceeds 2.5 / tau.
  * Errors: E_ARG (n_iter < 0, tau <= 0 or too large, mix outside (0, 1]),

@@ -1100,7 +1100,6 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
     HIPCHK(hipMemcpyAsync(c->d_Aobs, zero6, sizeof(zero6), hipMemcpyHostToDevice, c->stream));
     HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
     HIPCHK(launch_fill_int(c->d_status, 0, 1, c->stream));
-    HIPCHK(hipMemsetAsync(c->d_resid, 0, sizeof(double) * c->n_inst, c->stream));
     // the mixing starts from the density of the current orbitals (what v_Hxc was built from)
     HIPCHK(hipMemcpyAsync(c->d_rho_in, c->d_rho, sizeof(double) * size_t(c->ng_max) * c->n_inst,
                           hipMemcpyDeviceToDevice, c->stream));
@@ -1129,8 +1128,10 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
     HIPCHK(hipMemcpyAsync(c->jpre.data(), c->d_jpre, sizeof(double) * 3 * c->n_inst, hipMemcpyDeviceToHost,
                           c->stream));
     HIPCHK(hipMemcpyAsync(&status, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    if (residual)
+    if (residual && n_iter > 0)  // every iteration writes every instance's residual
         HIPCHK(hipMemcpyAsync(residual, c->d_resid, sizeof(double) * c->n_inst, hipMemcpyDeviceToHost, c->stream));
+    else if (residual)
+        std::fill(residual, residual + c->n_inst, 0.0);
     HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->steps_done = 0;
