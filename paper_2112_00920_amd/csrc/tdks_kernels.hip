@@ -357,7 +357,7 @@ hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, d
 // The orbitals stream through LDS in tiles of TP points of all bands (TP as large as
 // the tile buffer allows, so a tile is 8 elements per thread); the next tile is loaded
 // into registers while the current one is used.
-constexpr int kOrthTileCap = 2080;  // double2 slots of the tile buffer (nb (TP + 1) <= cap)
+constexpr int kOrthTileCap = 2080;  // tile elements (nb (TP + 1) <= cap), double2-sized slots
 constexpr int kOrthPer = 8;         // tile elements per thread (nb TP <= 2048)
 
 template <typename C>
@@ -375,12 +375,12 @@ __device__ __forceinline__ void orth_fetch(const C *u, int ng, int nb, int tp, i
 }
 
 template <typename C>
-__device__ __forceinline__ void orth_stage(const C *pre, int nb, int tp, double2 *T) {
+__device__ __forceinline__ void orth_stage(const C *pre, int nb, int tp, C *T) {
 #pragma unroll
     for (int q = 0; q < kOrthPer; ++q) {
         const int idx = threadIdx.x + 256 * q;
         const int b = idx / tp, pp = idx - b * tp;
-        if (b < nb) T[b * (tp + 1) + pp] = make_double2(double(pre[q].x), double(pre[q].y));
+        if (b < nb) T[b * (tp + 1) + pp] = pre[q];
     }
 }
 
@@ -389,10 +389,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
 void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
     constexpr int NB = kOrthMaxBands;
     static_assert(NB * NB <= kOrthTileCap, "the Gram matrix shares the tile buffer");
-    __shared__ double2 T[kOrthTileCap];  // tile [band][point], rows padded by one
-    __shared__ double2 Li[NB * NB];      // L^{-1} (lower triangle)
+    // tile [band][point] in the orbitals' own precision (rows padded by one); the Gram matrix
+    // (FP64) reuses its bytes between the two passes over the tiles
+    __shared__ double2 Tbuf[kOrthTileCap];
+    __shared__ double2 Li[NB * NB];  // L^{-1} (lower triangle)
     __shared__ int bad;
-    double2 *S = T;  // Gram matrix, then L (lower triangle): lives between the two tile passes
+    C *T = reinterpret_cast<C *>(Tbuf);
+    double2 *S = Tbuf;
     const int tid = threadIdx.x;
     const int2 pr = pairs[blockIdx.x];
     const DevInst &I = insts[pr.x];
@@ -419,12 +422,13 @@ void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
             const int e = tid + 256 * q;
             if (e < ne) {
                 const int i = e / nb, j = e - i * nb;
-                const double2 *ti = T + i * (tp + 1), *tj = T + j * (tp + 1);
+                const C *ti = T + i * (tp + 1), *tj = T + j * (tp + 1);
                 double sr = acc[q].x, si = acc[q].y;
-                for (int pp = 0; pp < np; ++pp) {  // conj(u_i) u_j
-                    const double2 a = ti[pp], b = tj[pp];
-                    sr += a.x * b.x + a.y * b.y;
-                    si += a.x * b.y - a.y * b.x;
+                for (int pp = 0; pp < np; ++pp) {  // conj(u_i) u_j, in FP64
+                    const C ca = ti[pp], cb = tj[pp];
+                    const double ax = ca.x, ay = ca.y, bx = cb.x, by = cb.y;
+                    sr += ax * bx + ay * by;
+                    si += ax * by - ay * bx;
                 }
                 acc[q] = make_double2(sr, si);
             }
@@ -500,9 +504,11 @@ void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
             if (b >= nb || pp >= np) continue;
             double xr = 0.0, xi = 0.0;
             for (int i = 0; i <= b; ++i) {
-                const double2 a = T[i * (tp + 1) + pp], l = Li[b * nb + i];
-                xr += a.x * l.x + a.y * l.y;  // a conj(l)
-                xi += a.y * l.x - a.x * l.y;
+                const C ca = T[i * (tp + 1) + pp];
+                const double ax = ca.x, ay = ca.y;
+                const double2 l = Li[b * nb + i];
+                xr += ax * l.x + ay * l.y;  // a conj(l)
+                xi += ay * l.x - ax * l.y;
             }
             C out;
             out.x = decltype(out.x)(xr);

@@ -132,3 +132,30 @@ def test_errors(tdks):
                 p.ground_state(*bad)
             assert e.value.code == _lib.E_ARG
         assert p.ground_state(0, 0.3, 0.5).shape == (1,)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ragged_grid_and_many_bands(tdks, precision):
+    """A 7^3 grid (z-segments of unequal length in the imaginary-time kernel) and 20
+    bands (the orthonormalisation's tiles of 64 points and its full 2 x 256 Gram
+    entries per thread) against the oracle's route, 2 iterations."""
+    sp = _species()
+    insts = [W.make_instance("diamond8", (7, 7, 7), 3, [sp], W.KSpec((2, 1, 1))),
+             W.make_instance("diamond8", (8, 8, 8), 20, [sp], W.KSpec((1, 1, 1)), group=1)]
+    u0s = [W.random_orbitals(80 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega) for i, inst in enumerate(insts)]
+    with tdks.Propagator(insts, precision=precision) as p:
+        til = p.tiling()
+        for i, u in enumerate(u0s):
+            p.load_orbitals(i, u)
+        res = p.ground_state(2, 0.2, 0.5)
+        got = [p.get_orbitals(i) for i in range(len(insts))]
+    _say(f"  {precision}: tiling {til}")
+    for i, inst in enumerate(insts):
+        u0 = u0s[i]
+        if precision == "fp32":
+            u0 = u0.astype(np.complex64).astype(np.complex128)
+        u, rho, v, r = G.imaginary_time_scf(System(inst), u0, 0.2, 0.5, 2)
+        eu = np.max(np.abs(got[i] - u))
+        _say(f"  {precision} instance {i} ({inst.grid}, {inst.n_bands} bands): u err {eu:.2e}, residual {res[i]:.3e}")
+        assert eu < (1e-10 if precision == "fp64" else 2e-5)
+        assert abs(res[i] - r[-1]) < (1e-9 if precision == "fp64" else 1e-3) * r[-1]
