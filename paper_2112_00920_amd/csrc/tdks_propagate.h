@@ -834,15 +834,18 @@ void k_propagate(PropArgs a) {
                         acc[z].x += wn.x;
                         acc[z].y += wn.y;
                         wc[z] = wn;
-                        if (active && TDKS_ZOK(z)) W[pw + plane * z] = wn;
+                        // the last term is only summed: the next writer of W is the store below
+                        if (active && TDKS_ZOK(z) && m < norder) W[pw + plane * z] = wn;
                     }
                 }
             }
             if (a.mode == MODE_APPLY) continue;
 
             // ---- new orbital: store; FP64 partials of density (in LDS or in this work item's
-            // global slot; only this thread touches these points) and current
-            __syncthreads();
+            // global slot; only this thread touches these points) and current.  No barrier is
+            // needed before the LDS store: after the last h application every read of W has
+            // passed the barrier that precedes the Taylor update, and each thread stores only
+            // its own points (with no Taylor terms W already holds the same values).
             const double fo = I.kw[k] * I.occ[b];
             const int ps = opq(pbase + plane * z0);
             if (active) {
