@@ -45,8 +45,8 @@ struct DevInst {
     const float *pt_gf;        // [nent] radial factors, FP32 copy
     const double *pt_gd;       // [nent] ... FP64 copy
     // chunks: up to 4 consecutive support points of one column image (consecutive j2,
-    // no periodic wrap inside), packed like entries (first point); radial factors
-    // g of the 4 points, zero-padded
+    // no periodic wrap inside), each packed as its first point's grid index p |
+    // (j2 - r + N3 + 3) << 13 | col << 20; radial factors g of the 4 points, zero-padded
     const uint32_t *chunk_pack;
     const float *chunk_gf;     // [nchunk][4]
     const double *chunk_gd;    // [nchunk][4]
@@ -97,7 +97,6 @@ struct PropArgs {
     int ncol_max;          // most projector column images of an instance in the launch
     int nent_max;          // most projector entries of an instance in the launch
     int nmaxd;             // largest N_d of the launch (phase tables)
-    int plane_max;         // largest N1 N2 of the launch (zeroed slack after the LDS orbital)
     int rho_lds;           // accumulate the FP64 density partial in LDS (else in the global slot)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch

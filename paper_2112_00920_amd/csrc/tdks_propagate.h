@@ -204,7 +204,7 @@ struct PropLds {
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
-                                            int nmaxd, int plane_max, int nat_max, int ntask_max, int block,
+                                            int nmaxd, int nat_max, int ntask_max, int block,
                                             int rho_lds) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
@@ -234,7 +234,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
-    return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max, a.nat_max, a.ntask_max,
+    return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max,
                     block, a.rho_lds).total;
 }
 
@@ -351,7 +351,7 @@ void k_propagate(PropArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = BS >> 6;
 
-    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.plane_max,
+    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd,
                                a.nat_max, a.ntask_max, BS, a.rho_lds);
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index

@@ -96,7 +96,7 @@ struct ShapeClass {
     bool nonorth;
     int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0;
     int wbeg = 0, wend = 0;
-    int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0, plane_max = 0;
+    int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
 };
 
 }  // namespace
@@ -516,7 +516,6 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.ncol_max = S.ncol_max;
     a.nent_max = S.nent_max;
     a.nmaxd = S.nmaxd;
-    a.plane_max = S.plane_max;
     a.rho_lds = S.rho_lds;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
@@ -809,7 +808,6 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         S.ncol_max = std::max(S.ncol_max, int(T.col_atom.size()));
         S.nent_max = std::max(S.nent_max, int(T.pt_pack.size()));
         S.nmaxd = std::max(S.nmaxd, std::max(I.N[0], std::max(I.N[1], I.N[2])));
-        S.plane_max = std::max(S.plane_max, I.N[0] * I.N[1]);
         S.nat_max = std::max(S.nat_max, T.nat);
         S.ntask_max = std::max(S.ntask_max, int(T.task.size()));
     }
