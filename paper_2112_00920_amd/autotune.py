@@ -40,12 +40,13 @@ def candidates(inst, precision) -> List[Dict]:
         waves = (4,) if b > 512 else (2, 4)
         for w in waves:
             for bpg in sorted({0, max(1, inst.n_bands // 2)}):
-                out.append({"block_size": b, "waves_per_simd": w, "bands_per_group": bpg, "k_per_group": 1})
+                for kpg in ((1, 4) if inst.n_k >= 4 else (1,)):
+                    out.append({"block_size": b, "waves_per_simd": w, "bands_per_group": bpg, "k_per_group": kpg})
     return out
 
 
 def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, min_items: int = 2048,
-         cache: Optional[str] = DEFAULT_CACHE, verbose: bool = False, max_candidates: int = 12) -> Dict:
+         cache: Optional[str] = DEFAULT_CACHE, verbose: bool = False, max_candidates: int = 32) -> Dict:
     """Returns the Propagator tiling options with the best measured updates/s.
 
     The sample is the instances of the most common grid shape, as many as it takes to
