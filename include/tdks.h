@@ -128,7 +128,8 @@ typedef struct tdks_options {
     void *alloc_user;     /* passed to alloc/free                                  */
     int bands_per_group;  /* bands propagated by one workgroup (0 = all)           */
     int k_per_group;      /* k-points per workgroup (0 = 4 for instances with at
-                             least 256 k-points, else 1)                          */
+                             least 256 k-points when the context has at least
+                             16384 (k, band group) items, else 1)                 */
     int block_size;       /* threads per workgroup (0 = automatic)                 */
     int graph_steps;      /* steps captured per HIP graph (0 = 16; <0 disables)    */
     int waves_per_simd;   /* occupancy target of the propagation kernel: 2 or 4

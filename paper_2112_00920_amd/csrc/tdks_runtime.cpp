@@ -825,6 +825,13 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
                         S.N[2], lds);
     }
     // work list: class-major, instance-major, then k groups and band groups
+    long long items1 = 0;  // work items with one k-point per workgroup
+    for (int i = 0; i < n_inst; ++i) {
+        const InstHost &I = c->inst[i];
+        const int bpg = (opt->bands_per_group > 0 && opt->bands_per_group < I.nb) ? opt->bands_per_group : I.nb;
+        items1 += (long long)I.nk * ((I.nb + bpg - 1) / bpg);
+    }
+    const bool big = items1 >= 16384;
     for (size_t s = 0; s < c->classes.size(); ++s) {
         ShapeClass &S = c->classes[s];
         S.wbeg = int(c->work.size());
@@ -832,11 +839,11 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
             InstHost &I = c->inst[i];
             if (I.cls != int(s)) continue;
             const int bpg = (opt->bands_per_group > 0 && opt->bands_per_group < I.nb) ? opt->bands_per_group : I.nb;
-            // k-points per workgroup: by default 4 for instances with many k-points (fewer
-            // table stagings and density slots; measured 2.4 % faster per step on the 512-k
-            // sub-simulations), else 1.  It depends on the instance only, so an instance gets
-            // the same work items, and bitwise the same results, inside a batch and alone.
-            const int kpg = opt->k_per_group > 0 ? opt->k_per_group : (I.nk >= 256 ? 4 : 1);
+            // k-points per workgroup: by default 4 for instances with at least 256 k-points in
+            // a context of at least 16384 single-k work items (64 per CU: fewer table stagings
+            // and density slots, 2.5 % faster per step on the two-step workload), else 1 (a
+            // lone 512-k instance needs its 512 workgroups to fill the GPU)
+            const int kpg = opt->k_per_group > 0 ? opt->k_per_group : (I.nk >= 256 && big ? 4 : 1);
             I.wbeg = int(c->work.size());
             int slot = 0;
             for (int k0 = 0; k0 < I.nk; k0 += kpg)
