@@ -447,9 +447,13 @@ void k_propagate(PropArgs a) {
         }
     }
 
-    R vz[ZL];
+    // v_loc + v_Hxc of the owned points: kept in registers for short segments and FP64, read
+    // from global memory (cache-resident) in every h application for long FP32 segments, whose
+    // 128-register budget it would otherwise push into spills (20^3: 14 % faster)
+    constexpr bool VREG = ZL <= 4 || sizeof(R) == 8;
+    R vz[VREG ? ZL : 1];
 #pragma unroll
-    for (int z = 0; z < ZL; ++z) {
+    for (int z = 0; z < (VREG ? ZL : 0); ++z) {
         vz[z] = (active && TDKS_ZOK(z)) ? vtot[pbase + plane * (z0 + z)] : R(0);
     }
 
@@ -710,7 +714,7 @@ void k_propagate(PropArgs a) {
                         zn[s] = W[pb + plane * zw];
                     }
                     const C cen = W[p];
-                    const R cv = c0 + vz[z];
+                    const R cv = c0 + (VREG ? vz[VREG ? z : 0] : vtot[p]);
                     C h;
                     h.x = cv * cen.x;
                     h.y = cv * cen.y;
