@@ -567,6 +567,12 @@ void k_propagate(PropArgs a) {
             const size_t orb = (size_t(k) * I.nb + b) * size_t(ng);
             C *ug = reinterpret_cast<C *>(I.u) + orb;
             const C *src = (a.mode == MODE_APPLY) ? reinterpret_cast<const C *>(a.apply_in) + orb : ug;
+            // Taylor sum: for short segments the terms are summed in registers,
+            //   acc = sum_m w_m, w_m = (-i dt/m) h w_{m-1};
+            // long FP32 segments, short of registers, evaluate the same polynomial by Horner's
+            // rule, v <- u + (-i dt/m) h v for m = 4, 3, 2, 1 (v = u first), re-reading u from
+            // global memory (cache-resident) and keeping v in LDS only (W), not in registers
+            constexpr bool HORNER = !VREG;
             C acc[ZL];
             const int pl = opq(pbase + plane * z0);
             // the orbital's loads are issued before the barrier, so their latency overlaps
@@ -817,7 +823,8 @@ void k_propagate(PropArgs a) {
                 } else {
                     // dt/m through a reciprocal of the (wave-uniform) order: one multiply
                     // instead of a double-precision division per thread
-                    const double rm = (m == 1) ? 1.0 : (m == 2) ? 0.5 : (m == 3) ? (1.0 / 3.0) : 0.25;
+                    const int mo = HORNER ? norder + 1 - m : m;  // Horner runs the orders backwards
+                    const double rm = (mo == 1) ? 1.0 : (mo == 2) ? 0.5 : (mo == 3) ? (1.0 / 3.0) : 0.25;
                     const R cm = R(a.dt * rm);
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
@@ -829,10 +836,20 @@ void k_propagate(PropArgs a) {
                             wn.x = cm * hz[z].y;
                             wn.y = -cm * hz[z].x;
                         }
-                        acc[z].x += wn.x;
-                        acc[z].y += wn.y;
-                        // the last term is only summed: the next writer of W is the store below
-                        if (active && TDKS_ZOK(z) && m < norder) W[pw + plane * z] = wn;
+                        if (HORNER) {  // v <- u + wn, into W also after the last order
+                            C u0;
+                            u0.x = R(0);
+                            u0.y = R(0);
+                            if (active && TDKS_ZOK(z)) u0 = gld(src + pw + plane * z);
+                            wn.x += u0.x;
+                            wn.y += u0.y;
+                            if (active && TDKS_ZOK(z)) W[pw + plane * z] = wn;
+                        } else {
+                            acc[z].x += wn.x;
+                            acc[z].y += wn.y;
+                            // the last term is only summed: the next writer of W is the store below
+                            if (active && TDKS_ZOK(z) && m < norder) W[pw + plane * z] = wn;
+                        }
                     }
                 }
             }
@@ -852,9 +869,15 @@ void k_propagate(PropArgs a) {
                 for (int z = 0; z < ZL; ++z) {
                     if (!TDKS_ZOK(z)) continue;
                     const int p = ps + plane * z;
-                    W[p] = acc[z];
-                    if (a.mode == MODE_STEP || ITIME) gst(ug + p, acc[z]);
-                    const double ux = double(acc[z].x), uy = double(acc[z].y);
+                    C fin;  // the new orbital (Horner: already in W, written by this thread)
+                    if (HORNER) {
+                        fin = W[p];
+                    } else {
+                        fin = acc[z];
+                        W[p] = fin;
+                    }
+                    if (a.mode == MODE_STEP || ITIME) gst(ug + p, fin);
+                    const double ux = double(fin.x), uy = double(fin.y);
                     const double r = fo * (ux * ux + uy * uy);
                     if (rho_lds)
                         RHO[p] = first ? r : RHO[p] + r;

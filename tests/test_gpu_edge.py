@@ -164,3 +164,29 @@ def test_ragged_z_segments(tdks, name, precision):
     assert grid[2] % til["zl"] != 0 or grid[2] < til["zl"]
     dj_o, u_o = _oracle(inst, u0, A)
     _check(name, dj, u, dj_o, u_o, precision)
+
+
+LONG_SEGMENT_CASES = {
+    # grid, threads per workgroup: one z-segment of 8 or 10 points per column (the FP32 kernel
+    # then sums the Taylor series by Horner's rule and reads the potential from memory)
+    "d8_8_zl8": ((8, 8, 8), 64),
+    "d8_10_zl10": ((10, 10, 10), 128),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(LONG_SEGMENT_CASES))
+def test_long_z_segments(tdks, name, precision):
+    grid, block = LONG_SEGMENT_CASES[name]
+    inst = W.make_instance("diamond8", grid, 3, [_species()], W.KSpec((2, 1, 1)))
+    u0 = W.random_orbitals(17, inst.n_k, inst.n_bands, grid, inst.omega)
+    A = W.Field("kick", 1e-3).table(4, 0.02)
+    with tdks.Propagator([inst], precision=precision, block_size=block) as p:
+        til = p.tiling()
+        p.load_orbitals(0, u0)
+        p.step(A)
+        dj, u = p.current()[0], p.get_orbitals(0)
+    _say(f"  {name} {precision}: tiling {til}")
+    assert til["zl"] == grid[2]
+    dj_o, u_o = _oracle(inst, u0, A)
+    _check(name, dj, u, dj_o, u_o, precision)
