@@ -17,19 +17,13 @@ static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream
     return hipGetLastError();
 }
 
-// the imaginary-time variants read the projector tables from global memory only (no
-// LDS-staged copy), which halves their instantiations; SL is a speed choice, not a result
 template <bool IT>
 static hipError_t dispatch(const PropArgs &a, int n_items, int block, int zl, int minw, int sl, int ragged,
                            hipStream_t s) {
 #define TDKS_CASE(Z, M, O, RG)                                                                      \
     if (ragged == RG && zl == Z && block <= M && minw == O) {                                       \
-        if constexpr (IT) {                                                                         \
-            return launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                             \
-        } else {                                                                                    \
-            return sl ? launch_zl<Z, M, O, true, RG>(a, n_items, block, s)                          \
-                      : launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                        \
-        }                                                                                           \
+        return sl ? launch_zl<Z, M, O, true, RG>(a, n_items, block, s)                              \
+                  : launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                            \
     }
 #define TDKS_CASE_EVEN(Z, M, O) TDKS_CASE(Z, M, O, false)
 #define TDKS_CASE_RAGGED(Z, M, O) TDKS_CASE(Z, M, O, true)
