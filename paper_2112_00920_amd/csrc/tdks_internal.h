@@ -122,7 +122,8 @@ hipError_t launch_fill_int(int *p, int v, int n, hipStream_t s);
 hipError_t launch_convert_in(const double *src, void *dst, size_t n_complex, int fp64, hipStream_t s);
 hipError_t launch_convert_out(const void *src, double *dst, size_t n_complex, int fp64, hipStream_t s);
 hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, double *out, hipStream_t s);
-hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int fp64, int *status, hipStream_t s);
+hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int nb_max, int fp64, int *status,
+                       hipStream_t s);
 hipError_t launch_mix(const DevInst *insts, int n_inst, int ng_max, double *rho, double *rho_in, double alpha,
                       double *resid, hipStream_t s);
 

@@ -353,19 +353,34 @@ hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, d
 // Ground-state preparation: Cholesky orthonormalisation of the bands of one k-point,
 // S = U^H U dV = L L^H, U <- U L^{-H} (the first band keeps its direction).  One
 // workgroup per (instance, k); FP64 throughout, orbitals read twice and written once.
-// Each Gram entry is summed by one thread in point order, so results are reproducible.
 // The orbitals stream through LDS in tiles of TP points of all bands (TP as large as
 // the tile buffer allows, so a tile is 8 elements per thread); the next tile is loaded
-// into registers while the current one is used.
-constexpr int kOrthTileCap = 2080;  // tile elements (nb (TP + 1) <= cap), double2-sized slots
+// into registers while the current one is used.  Both dense products run on the FP64
+// matrix cores (v_mfma_f64_16x16x4: A 16 x 4, B 4 x 16, D 16 x 16; lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 r + l / 16][l % 16] in its
+// register r):
+//  - Gram matrix: with V = [Re U, Im U] (points x bands), S = Re^T Re + Im^T Im +
+//    i (Re^T Im - (Re^T Im)^T), three real products over 4-point slices; each of the
+//    4 waves sums every 4th slice and the wave sums are added in wave order, so the
+//    result does not depend on timing;
+//  - transform: U L^{-H} over 16-point blocks, four real products per 4 bands, with
+//    the L^{-1} operands kept in registers for the whole pass.
+constexpr int kOrthTileCap = 2080;  // tile elements (nb (TP + 1) <= cap), double2 slots
 constexpr int kOrthPer = 8;         // tile elements per thread (nb TP <= 2048)
 
+typedef double orth_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ orth_d4 mfma64(double a, double b, orth_d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 template <typename C>
-__device__ __forceinline__ void orth_fetch(const C *u, int ng, int nb, int tp, int p0, C *pre) {
+__device__ __forceinline__ void orth_fetch(const C *u, int ng, int nb, int lt, int p0, C *pre) {
+    const int tm = (1 << lt) - 1;
 #pragma unroll
     for (int q = 0; q < kOrthPer; ++q) {
         const int idx = threadIdx.x + 256 * q;
-        const int b = idx / tp, pp = idx - b * tp;
+        const int b = idx >> lt, pp = idx & tm;
         C x;
         x.x = 0;
         x.y = 0;
@@ -374,71 +389,112 @@ __device__ __forceinline__ void orth_fetch(const C *u, int ng, int nb, int tp, i
     }
 }
 
+// stores the prefetched elements as FP64; points past the grid end are zero
 template <typename C>
-__device__ __forceinline__ void orth_stage(const C *pre, int nb, int tp, C *T) {
+__device__ __forceinline__ void orth_stage(const C *pre, int nb, int lt, double2 *T) {
+    const int tm = (1 << lt) - 1;
 #pragma unroll
     for (int q = 0; q < kOrthPer; ++q) {
         const int idx = threadIdx.x + 256 * q;
-        const int b = idx / tp, pp = idx - b * tp;
-        if (b < nb) T[b * (tp + 1) + pp] = pre[q];
+        const int b = idx >> lt, pp = idx & tm;
+        if (b < nb) T[b * (tm + 2) + pp] = make_double2(double(pre[q].x), double(pre[q].y));
     }
 }
 
-template <typename C>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+// NBB: 16-band blocks (1: nb <= 16, 2: nb <= 32; the latter needs the larger register budget)
+template <typename C, int NBB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBB == 1 ? 3 : 2, 8)))
 void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
     constexpr int NB = kOrthMaxBands;
     static_assert(NB * NB <= kOrthTileCap, "the Gram matrix shares the tile buffer");
-    // tile [band][point] in the orbitals' own precision (rows padded by one); the Gram matrix
-    // (FP64) reuses its bytes between the two passes over the tiles
-    __shared__ double2 Tbuf[kOrthTileCap];
+    static_assert(16 * NBB <= NB, "band blocks");
+    // tile [band][point] in FP64 (rows padded by one); the Gram matrix reuses its bytes
+    // between the two passes over the tiles
+    __shared__ double2 T[kOrthTileCap];
     __shared__ double2 Li[NB * NB];  // L^{-1} (lower triangle)
     __shared__ int bad;
-    C *T = reinterpret_cast<C *>(Tbuf);
-    double2 *S = Tbuf;
-    const int tid = threadIdx.x;
+    double2 *S = T;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lm = lane & 15, lk = lane >> 4;
     const int2 pr = pairs[blockIdx.x];
     const DevInst &I = insts[pr.x];
     const int nb = I.nb, ng = I.ng;
     C *u = reinterpret_cast<C *>(I.u) + size_t(pr.y) * nb * ng;
-    int tp = 16;
-    while (tp < 512 && nb * 2 * tp <= 256 * kOrthPer && nb * (2 * tp + 1) <= kOrthTileCap) tp *= 2;
-    const int ne = nb * nb;
-    double2 acc[(NB * NB) / 256];
-#pragma unroll
-    for (int q = 0; q < (NB * NB) / 256; ++q) acc[q] = make_double2(0.0, 0.0);
+    int lt = 4;  // tiles of 2^lt points
+    while (lt < 9 && (nb << (lt + 1)) <= 256 * kOrthPer && nb * ((2 << lt) + 1) <= kOrthTileCap) ++lt;
+    const int tp = 1 << lt, ld = tp + 1;
     if (tid == 0) bad = 0;
     C pre[kOrthPer];
-    // ---- Gram matrix over tiles of points
-    orth_fetch(u, ng, nb, tp, 0, pre);
+    // ---- Gram matrix: per wave, blocks (I, J) of Re^T Re, Im^T Im and Re^T Im
+    orth_d4 rr[NBB][NBB], ii[NBB][NBB], ri[NBB][NBB];
+#pragma unroll
+    for (int x = 0; x < NBB; ++x)
+#pragma unroll
+        for (int y = 0; y < NBB; ++y) rr[x][y] = ii[x][y] = ri[x][y] = orth_d4{0.0, 0.0, 0.0, 0.0};
+    orth_fetch(u, ng, nb, lt, 0, pre);
     for (int p0 = 0; p0 < ng; p0 += tp) {
         const int np = (ng - p0 < tp) ? ng - p0 : tp;
         __syncthreads();  // previous tile consumed
-        orth_stage(pre, nb, tp, T);
+        orth_stage(pre, nb, lt, T);
         __syncthreads();
-        if (p0 + tp < ng) orth_fetch(u, ng, nb, tp, p0 + tp, pre);
+        if (p0 + tp < ng) orth_fetch(u, ng, nb, lt, p0 + tp, pre);
+        const int nsl = (np + 3) >> 2;  // 4-point slices holding grid points
+        for (int sl = wave; sl < nsl; sl += 4) {
+            const int pp = 4 * sl + lk;
+            double2 v[NBB];
 #pragma unroll
-        for (int q = 0; q < (NB * NB) / 256; ++q) {
-            const int e = tid + 256 * q;
-            if (e < ne) {
-                const int i = e / nb, j = e - i * nb;
-                const C *ti = T + i * (tp + 1), *tj = T + j * (tp + 1);
-                double sr = acc[q].x, si = acc[q].y;
-                for (int pp = 0; pp < np; ++pp) {  // conj(u_i) u_j, in FP64
-                    const C ca = ti[pp], cb = tj[pp];
-                    const double ax = ca.x, ay = ca.y, bx = cb.x, by = cb.y;
-                    sr += ax * bx + ay * by;
-                    si += ax * by - ay * bx;
-                }
-                acc[q] = make_double2(sr, si);
+            for (int x = 0; x < NBB; ++x) {
+                const int band = 16 * x + lm;
+                v[x] = band < nb ? T[band * ld + pp] : make_double2(0.0, 0.0);
             }
+#pragma unroll
+            for (int x = 0; x < NBB; ++x)
+#pragma unroll
+                for (int y = 0; y < NBB; ++y) {
+                    rr[x][y] = mfma64(v[x].x, v[y].x, rr[x][y]);
+                    ii[x][y] = mfma64(v[x].y, v[y].y, ii[x][y]);
+                    ri[x][y] = mfma64(v[x].x, v[y].y, ri[x][y]);
+                }
         }
     }
-    __syncthreads();  // last tile consumed before S overwrites it
+    // wave sums in wave order: S.x <- sum (Re^T Re + Im^T Im), S.y <- sum Re^T Im
+    for (int w = 0; w < 4; ++w) {
+        __syncthreads();  // last tile consumed / previous wave's sums written
+        if (wave == w) {
+#pragma unroll
+            for (int x = 0; x < NBB; ++x)
+#pragma unroll
+                for (int y = 0; y < NBB; ++y)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = 16 * x + 4 * r + lk, j = 16 * y + lm;
+                        if (i < nb && j < nb) {
+                            double2 t = make_double2(rr[x][y][r] + ii[x][y][r], ri[x][y][r]);
+                            if (w > 0) {
+                                const double2 o = S[i * nb + j];
+                                t = make_double2(o.x + t.x, o.y + t.y);
+                            }
+                            S[i * nb + j] = t;
+                        }
+                    }
+        }
+    }
+    __syncthreads();
+    const int ne = nb * nb;
+    double2 sv[(NB * NB) / 256];
+#pragma unroll
+    for (int q = 0; q < (NB * NB) / 256; ++q) {  // Im S_ij = (Re^T Im)_ij - (Re^T Im)_ji
+        const int e = tid + 256 * q;
+        if (e < ne) {
+            const int i = e / nb, j = e - i * nb;
+            sv[q] = make_double2(S[e].x * I.dV, (S[e].y - S[j * nb + i].y) * I.dV);
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < (NB * NB) / 256; ++q) {
         const int e = tid + 256 * q;
-        if (e < ne) S[e] = make_double2(acc[q].x * I.dV, acc[q].y * I.dV);
+        if (e < ne) S[e] = sv[q];
     }
     __syncthreads();
     // ---- Cholesky S = L L^H in place, one column per round (rows in parallel)
@@ -488,43 +544,86 @@ void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
             Li[i * nb + c] = make_double2(v.x * r, v.y * r);
         }
     }
-    // ---- U <- U L^{-H}: u_new_b(p) = sum_{i<=b} u_i(p) conj(Li_bi), tile by tile (a tile is
-    // written only after it was read into LDS; the prefetch reads the next, untouched tile)
-    orth_fetch(u, ng, nb, tp, 0, pre);
+    __syncthreads();
+    // ---- U <- U L^{-H}: D[p][b] = sum_k U[p][k] conj(Li[b][k]) with B operand
+    // B[k][b] = Li[b][k] per 4-band step k4 and 16-band output block y (lane: b = 16 y + l % 16,
+    // k = 4 k4 + l / 16; zero outside the bands, and above the diagonal by construction).
+    // Re D = Re U Re Li^T + Im U Im Li^T, Im D = Im U Re Li^T - Re U Im Li^T.
+    constexpr int NK4 = 4 * NBB;
+    double bx[NK4][NBB], by[NK4][NBB];
+#pragma unroll
+    for (int k4 = 0; k4 < NK4; ++k4)
+#pragma unroll
+        for (int y = 0; y < NBB; ++y) {
+            const int b = 16 * y + lm, k = 4 * k4 + lk;
+            const double2 l = (b < nb && k < nb) ? Li[b * nb + k] : make_double2(0.0, 0.0);
+            bx[k4][y] = l.x;
+            by[k4][y] = l.y;
+        }
+    const int nk4 = (nb + 3) >> 2;
+    // a tile is written only after it was read into LDS; the prefetch reads the next,
+    // untouched tile
+    orth_fetch(u, ng, nb, lt, 0, pre);
     for (int p0 = 0; p0 < ng; p0 += tp) {
         const int np = (ng - p0 < tp) ? ng - p0 : tp;
-        __syncthreads();  // Li ready / previous tile consumed
-        orth_stage(pre, nb, tp, T);
+        __syncthreads();  // previous tile consumed
+        orth_stage(pre, nb, lt, T);
         __syncthreads();
-        if (p0 + tp < ng) orth_fetch(u, ng, nb, tp, p0 + tp, pre);
+        if (p0 + tp < ng) orth_fetch(u, ng, nb, lt, p0 + tp, pre);
+        const int npb = (np + 15) >> 4;  // 16-point blocks holding grid points
+        for (int pb = wave; pb < npb; pb += 4) {
+            orth_d4 dr[NBB], di[NBB];
 #pragma unroll
-        for (int q = 0; q < kOrthPer; ++q) {
-            const int idx = tid + 256 * q;
-            const int b = idx / tp, pp = idx - b * tp;
-            if (b >= nb || pp >= np) continue;
-            double xr = 0.0, xi = 0.0;
-            for (int i = 0; i <= b; ++i) {
-                const C ca = T[i * (tp + 1) + pp];
-                const double ax = ca.x, ay = ca.y;
-                const double2 l = Li[b * nb + i];
-                xr += ax * l.x + ay * l.y;  // a conj(l)
-                xi += ay * l.x - ax * l.y;
+            for (int y = 0; y < NBB; ++y) dr[y] = di[y] = orth_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k4 = 0; k4 < NK4; ++k4) {
+                if (k4 < nk4) {
+                    const int band = 4 * k4 + lk;
+                    const double2 a = band < nb ? T[band * ld + 16 * pb + lm] : make_double2(0.0, 0.0);
+                    const double nax = -a.x;
+#pragma unroll
+                    for (int y = 0; y < NBB; ++y) {
+                        if (4 * k4 <= 16 * y + 15) {  // bands k contribute to outputs b >= k only
+                            dr[y] = mfma64(a.x, bx[k4][y], dr[y]);
+                            dr[y] = mfma64(a.y, by[k4][y], dr[y]);
+                            di[y] = mfma64(a.y, bx[k4][y], di[y]);
+                            di[y] = mfma64(nax, by[k4][y], di[y]);
+                        }
+                    }
+                }
             }
-            C out;
-            out.x = decltype(out.x)(xr);
-            out.y = decltype(out.y)(xi);
-            u[size_t(b) * ng + p0 + pp] = out;
+#pragma unroll
+            for (int y = 0; y < NBB; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int b = 16 * y + lm, pp = 16 * pb + 4 * r + lk;
+                    if (b < nb && pp < np) {
+                        C out;
+                        out.x = decltype(out.x)(dr[y][r]);
+                        out.y = decltype(out.y)(di[y][r]);
+                        u[size_t(b) * ng + p0 + pp] = out;
+                    }
+                }
         }
     }
 }
 
-hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int fp64, int *status,
+hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int nb_max, int fp64, int *status,
                        hipStream_t s) {
     if (n_pairs <= 0) return hipSuccess;
-    if (fp64)
-        hipLaunchKernelGGL(k_orth<double2>, dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
-    else
-        hipLaunchKernelGGL(k_orth<float2>, dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+    if (nb_max < 1 || nb_max > kOrthMaxBands) return hipErrorInvalidValue;
+    const bool two = nb_max > 16;
+    if (fp64) {
+        if (two)
+            hipLaunchKernelGGL((k_orth<double2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+        else
+            hipLaunchKernelGGL((k_orth<double2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+    } else {
+        if (two)
+            hipLaunchKernelGGL((k_orth<float2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+        else
+            hipLaunchKernelGGL((k_orth<float2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+    }
     return hipGetLastError();
 }
 

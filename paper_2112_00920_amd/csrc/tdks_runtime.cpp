@@ -1105,6 +1105,8 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
         if (!c->d_rho_in || !c->d_resid || !c->d_status) return fail(TDKS_E_OOM, "ground-state buffers");
     }
     const bool scf = (c->opt.hxc_mode == TDKS_HXC_SCF);
+    int nb_max = 1;
+    for (int i = 0; i < c->n_inst; ++i) nb_max = std::max(nb_max, c->inst[i].nb);
     const double zero6[6] = {0, 0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(c->d_Aobs, zero6, sizeof(zero6), hipMemcpyHostToDevice, c->stream));
     HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
@@ -1120,7 +1122,7 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
             HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
                                     c->stream));
         }
-        HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, c->fp64, c->d_status, c->stream));
+        HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, nb_max, c->fp64, c->d_status, c->stream));
         CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jobs, MODE_DENSITY));
         HIPCHK(launch_mix(c->d_insts, c->n_inst, c->ng_max, c->d_rho, c->d_rho_in, scf ? mix : 1.0, c->d_resid,
                           c->stream));
