@@ -159,3 +159,25 @@ def test_ragged_grid_and_many_bands(tdks, precision):
         _say(f"  {precision} instance {i} ({inst.grid}, {inst.n_bands} bands): u err {eu:.2e}, residual {res[i]:.3e}")
         assert eu < (1e-10 if precision == "fp64" else 2e-5)
         assert abs(res[i] - r[-1]) < (1e-9 if precision == "fp64" else 1e-3) * r[-1]
+
+
+@pytest.mark.parametrize("bands", [(1, 16), (17, 32)])
+def test_band_counts_at_block_edges(tdks, bands):
+    """Band counts at the edges of the orthonormalisation's 16-band blocks: one band and
+    a full block (one block), one past a block and the maximum of 32 (two blocks; the
+    launch takes the larger count's variant), FP64 against the oracle's route."""
+    sp = _species()
+    insts = [W.make_instance("diamond8", (8, 8, 8), nb, [sp], W.KSpec((1, 1, 1)), group=g)
+             for g, nb in enumerate(bands)]
+    u0s = [W.random_orbitals(90 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega) for i, inst in enumerate(insts)]
+    with tdks.Propagator(insts, precision="fp64") as p:
+        for i, u in enumerate(u0s):
+            p.load_orbitals(i, u)
+        res = p.ground_state(2, 0.2, 0.5)
+        got = [p.get_orbitals(i) for i in range(len(insts))]
+    for i, inst in enumerate(insts):
+        u, rho, v, r = G.imaginary_time_scf(System(inst), u0s[i], 0.2, 0.5, 2)
+        eu = np.max(np.abs(got[i] - u))
+        _say(f"  {inst.n_bands} bands: u err {eu:.2e}, residual {res[i]:.3e}")
+        assert eu < 1e-10
+        assert abs(res[i] - r[-1]) < 1e-9 * r[-1]
