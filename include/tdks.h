@@ -209,7 +209,9 @@ int tdks_steps_done(tdks_ctx *ctx);
  * after tdks_load_orbitals) and the step counter is reset.  residual (HOST
  * [n_inst], may be NULL) receives the last iteration's residual per instance.
  * n_iter = 0 only recomputes rho, v_Hxc and J_pre (residual receives zeros).
- * Synchronises.
+ * The first call allocates its buffers through the context's allocator: one
+ * FP64 density partial per k-point of every instance (8 N_g n_k bytes each),
+ * the mixing's input density and the residuals.  Synchronises.
  * Stability: the Taylor-4 filter is bounded for tau lambda_max(h_k) < 2.78; the
  * call rejects tau whose kinetic bound alone exceeds 2.5 / tau.
  * Errors: E_ARG (n_iter < 0, tau <= 0 or too large, mix outside (0, 1]),

@@ -79,10 +79,8 @@ struct WorkItem {
 // STEP: real-time Taylor-4 step + density/current partials; OBSERVE: partials only;
 // APPLY: one h application; ITIME: imaginary-time Taylor-4 step exp(-tau h) (dt holds tau),
 // orbitals stored, no partials; PREDICT: real-time step whose orbitals are not stored, density
-// partials only (the predictor of the predictor-corrector step); DENSITY: density partials of the
-// present orbitals only
-enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3, MODE_PREDICT = 4,
-                  MODE_DENSITY = 5 };
+// partials only (the predictor of the predictor-corrector step)
+enum Mode : int { MODE_STEP = 0, MODE_OBSERVE = 1, MODE_APPLY = 2, MODE_ITIME = 3, MODE_PREDICT = 4 };
 
 constexpr int kOrthMaxBands = 32;  // bands per k the orthonormalisation kernel holds in LDS
 
@@ -123,7 +121,9 @@ hipError_t launch_convert_in(const double *src, void *dst, size_t n_complex, int
 hipError_t launch_convert_out(const void *src, double *dst, size_t n_complex, int fp64, hipStream_t s);
 hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, double *out, hipStream_t s);
 hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int nb_max, int fp64, int *status,
-                       hipStream_t s);
+                       double *rho_k, int ng_max, hipStream_t s);
+hipError_t launch_reduce_k(const DevInst *insts, int n_inst, const int *first, const double *rho_k, int ng_max,
+                           double *rho, hipStream_t s);
 hipError_t launch_mix(const DevInst *insts, int n_inst, int ng_max, double *rho, double *rho_in, double alpha,
                       double *resid, hipStream_t s);
 

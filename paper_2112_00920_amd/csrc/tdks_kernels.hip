@@ -74,6 +74,27 @@ hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, dou
     return hipGetLastError();
 }
 
+// Density of each instance from per-k partials rho_k[pair][r] (pairs of instance i are
+// first[i] .. first[i+1]-1), summed in k order: the ground-state iteration's density.
+__global__ __launch_bounds__(256) void k_reduce_k(const DevInst *insts, const int *first, const double *rho_k,
+                                                  int ng_max, double *rho) {
+    const int inst = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= insts[inst].ng) return;
+    double s = 0.0;
+#pragma unroll 8
+    for (int q = first[inst]; q < first[inst + 1]; ++q) s += rho_k[size_t(q) * ng_max + p];
+    rho[size_t(inst) * ng_max + p] = s;
+}
+
+hipError_t launch_reduce_k(const DevInst *insts, int n_inst, const int *first, const double *rho_k, int ng_max,
+                           double *rho, hipStream_t s) {
+    if (n_inst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_k, dim3((ng_max + 255) / 256, n_inst), dim3(256), 0, s, insts, first, rho_k,
+                       ng_max, rho);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Hartree + LDA, one workgroup per instance.  Poisson: rho(G) by a separable
 // discrete Fourier transform (each line of N_d <= 32 points held in registers,
@@ -365,6 +386,9 @@ hipError_t launch_norms(const void *u, int n_orb, int ng, double dV, int fp64, d
 //    result does not depend on timing;
 //  - transform: U L^{-H} over 16-point blocks, four real products per 4 bands, with
 //    the L^{-1} operands kept in registers for the whole pass.
+// With rho_k given, the kernel also writes this k-point's FP64 density partial
+// w_k sum_b f_b |u_b(r)|^2 of the stored (rounded) new orbitals to rho_k[pair][r]
+// (bands summed by a fixed butterfly), so that no pass re-reads the orbitals for it.
 constexpr int kOrthTileCap = 2080;  // tile elements (nb (TP + 1) <= cap), double2 slots
 constexpr int kOrthPer = 8;         // tile elements per thread (nb TP <= 2048)
 
@@ -401,17 +425,20 @@ __device__ __forceinline__ void orth_stage(const C *pre, int nb, int lt, double2
     }
 }
 
-// NBB: 16-band blocks (1: nb <= 16, 2: nb <= 32; the latter needs the larger register budget)
+// NBB: 16-band blocks (1: nb <= 16, 2: nb <= 32; the latter needs the larger register budget).
+// With one block, L^{-1} takes 4 KB of LDS, so 4 workgroups fit a CU (FP32 orbitals: within
+// the 128 registers that 4 waves per SIMD leave).
 template <typename C, int NBB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBB == 1 ? 3 : 2, 8)))
-void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(NBB == 2 ? 2 : (sizeof(C) == 8 ? 4 : 3), 8)))
+void k_orth(const DevInst *insts, const int2 *pairs, int *status, double *rho_k, int ng_max) {
     constexpr int NB = kOrthMaxBands;
     static_assert(NB * NB <= kOrthTileCap, "the Gram matrix shares the tile buffer");
     static_assert(16 * NBB <= NB, "band blocks");
     // tile [band][point] in FP64 (rows padded by one); the Gram matrix reuses its bytes
     // between the two passes over the tiles
     __shared__ double2 T[kOrthTileCap];
-    __shared__ double2 Li[NB * NB];  // L^{-1} (lower triangle)
+    __shared__ double2 Li[(16 * NBB) * (16 * NBB)];  // L^{-1} (lower triangle), row stride nb
     __shared__ int bad;
     double2 *S = T;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -561,6 +588,10 @@ void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
             by[k4][y] = l.y;
         }
     const int nk4 = (nb + 3) >> 2;
+    double fo[NBB];  // w_k f_b of the lane's output bands (zero past the last band)
+#pragma unroll
+    for (int y = 0; y < NBB; ++y) fo[y] = (16 * y + lm < nb) ? I.kw[pr.y] * I.occ[16 * y + lm] : 0.0;
+    double *rk = rho_k ? rho_k + size_t(blockIdx.x) * ng_max : nullptr;
     // a tile is written only after it was read into LDS; the prefetch reads the next,
     // untouched tile
     orth_fetch(u, ng, nb, lt, 0, pre);
@@ -592,37 +623,47 @@ void k_orth(const DevInst *insts, const int2 *pairs, int *status) {
                     }
                 }
             }
+            double rs[4] = {0.0, 0.0, 0.0, 0.0};  // density at the points 16 pb + 4 r + l / 16
 #pragma unroll
             for (int y = 0; y < NBB; ++y)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int b = 16 * y + lm, pp = 16 * pb + 4 * r + lk;
-                    if (b < nb && pp < np) {
-                        C out;
-                        out.x = decltype(out.x)(dr[y][r]);
-                        out.y = decltype(out.y)(di[y][r]);
-                        u[size_t(b) * ng + p0 + pp] = out;
-                    }
+                    C out;
+                    out.x = decltype(out.x)(dr[y][r]);
+                    out.y = decltype(out.y)(di[y][r]);
+                    if (b < nb && pp < np) u[size_t(b) * ng + p0 + pp] = out;
+                    const double ox = double(out.x), oy = double(out.y);
+                    rs[r] = fma(fo[y], ox * ox + oy * oy, rs[r]);
                 }
+            if (rk) {
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1)  // sum over the 16 bands of a row
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rs[r] += __shfl_xor(rs[r], off);
+                const int pp = 16 * pb + 4 * lm + lk;  // lane l % 16 = r < 4 writes row r
+                const double v = lm == 0 ? rs[0] : lm == 1 ? rs[1] : lm == 2 ? rs[2] : rs[3];
+                if (lm < 4 && pp < np) rk[p0 + pp] = v;
+            }
         }
     }
 }
 
 hipError_t launch_orth(const DevInst *insts, const int2 *pairs, int n_pairs, int nb_max, int fp64, int *status,
-                       hipStream_t s) {
+                       double *rho_k, int ng_max, hipStream_t s) {
     if (n_pairs <= 0) return hipSuccess;
     if (nb_max < 1 || nb_max > kOrthMaxBands) return hipErrorInvalidValue;
     const bool two = nb_max > 16;
     if (fp64) {
         if (two)
-            hipLaunchKernelGGL((k_orth<double2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+            hipLaunchKernelGGL((k_orth<double2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status, rho_k, ng_max);
         else
-            hipLaunchKernelGGL((k_orth<double2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+            hipLaunchKernelGGL((k_orth<double2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status, rho_k, ng_max);
     } else {
         if (two)
-            hipLaunchKernelGGL((k_orth<float2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+            hipLaunchKernelGGL((k_orth<float2, 2>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status, rho_k, ng_max);
         else
-            hipLaunchKernelGGL((k_orth<float2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status);
+            hipLaunchKernelGGL((k_orth<float2, 1>), dim3(n_pairs), dim3(256), 0, s, insts, pairs, status, rho_k, ng_max);
     }
     return hipGetLastError();
 }

@@ -885,8 +885,8 @@ void k_propagate(PropArgs a) {
                         rp[p] = first ? r : rp[p] + r;
                 }
             }
-            // no current: imaginary time, predictor, density only
-            if (ITIME || a.mode == MODE_PREDICT || a.mode == MODE_DENSITY) continue;
+            // no current: imaginary time, predictor
+            if (ITIME || a.mode == MODE_PREDICT) continue;
             __syncthreads();
             // per-thread sums over the owned points in the orbital precision, FP64 beyond.
             // Summed over the whole periodic grid, sum_p Im(conj(u_p) (u_{p+s} - u_{p-s}))

@@ -134,6 +134,8 @@ struct tdks_ctx {
     int2 *d_pairs = nullptr;
     int n_pairs = 0;
     int *d_status = nullptr;
+    double *d_rho_k = nullptr;   // ground state: per-(instance, k) density partials [n_pairs][ng_max]
+    int *d_pair_first = nullptr; // first pair of each instance [n_inst + 1]
     int steps_done = 0;
     hipGraphExec_t g_chunk = nullptr, g_one = nullptr;
     int chunk = 16;
@@ -1099,10 +1101,15 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
             for (int k = 0; k < c->inst[i].nk; ++k) pairs.push_back(make_int2(i, k));
         CHK(upload(c, &c->d_pairs, pairs));
         c->n_pairs = int(pairs.size());
+        std::vector<int> first(1, 0);
+        for (int i = 0; i < c->n_inst; ++i) first.push_back(first.back() + c->inst[i].nk);
+        CHK(upload(c, &c->d_pair_first, first));
+        c->d_rho_k = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_pairs));
         c->d_rho_in = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_inst));
         c->d_resid = static_cast<double *>(c->alloc(sizeof(double) * c->n_inst));
         c->d_status = static_cast<int *>(c->alloc(sizeof(int)));
-        if (!c->d_rho_in || !c->d_resid || !c->d_status) return fail(TDKS_E_OOM, "ground-state buffers");
+        if (!c->d_rho_in || !c->d_resid || !c->d_status || !c->d_rho_k)
+            return fail(TDKS_E_OOM, "ground-state buffers");
     }
     const bool scf = (c->opt.hxc_mode == TDKS_HXC_SCF);
     int nb_max = 1;
@@ -1122,8 +1129,9 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
             HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
                                     c->stream));
         }
-        HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, nb_max, c->fp64, c->d_status, c->stream));
-        CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jobs, MODE_DENSITY));
+        HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, nb_max, c->fp64, c->d_status, c->d_rho_k, c->ng_max,
+                           c->stream));
+        HIPCHK(launch_reduce_k(c->d_insts, c->n_inst, c->d_pair_first, c->d_rho_k, c->ng_max, c->d_rho, c->stream));
         HIPCHK(launch_mix(c->d_insts, c->n_inst, c->ng_max, c->d_rho, c->d_rho_in, scf ? mix : 1.0, c->d_resid,
                           c->stream));
         if (scf)
