@@ -1095,21 +1095,40 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
                         " need tau * bound <= 2.5)", i, tau, lam);
     }
     CHK(sync_in(c));
-    if (!c->d_pairs) {
+    if (c->n_pairs == 0) {  // first call: its buffers (n_pairs is set only once all exist)
         std::vector<int2> pairs;
         for (int i = 0; i < c->n_inst; ++i)
             for (int k = 0; k < c->inst[i].nk; ++k) pairs.push_back(make_int2(i, k));
-        CHK(upload(c, &c->d_pairs, pairs));
-        c->n_pairs = int(pairs.size());
         std::vector<int> first(1, 0);
         for (int i = 0; i < c->n_inst; ++i) first.push_back(first.back() + c->inst[i].nk);
-        CHK(upload(c, &c->d_pair_first, first));
-        c->d_rho_k = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_pairs));
-        c->d_rho_in = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_inst));
-        c->d_resid = static_cast<double *>(c->alloc(sizeof(double) * c->n_inst));
-        c->d_status = static_cast<int *>(c->alloc(sizeof(int)));
-        if (!c->d_rho_in || !c->d_resid || !c->d_status || !c->d_rho_k)
-            return fail(TDKS_E_OOM, "ground-state buffers");
+        auto drop = [c]() {  // a failed set-up leaves nothing behind, so the next call starts over
+            c->release(c->d_pairs);
+            c->release(c->d_pair_first);
+            c->release(c->d_rho_k);
+            c->release(c->d_rho_in);
+            c->release(c->d_resid);
+            c->release(c->d_status);
+            c->d_pairs = nullptr;
+            c->d_pair_first = nullptr;
+            c->d_rho_k = c->d_rho_in = c->d_resid = nullptr;
+            c->d_status = nullptr;
+        };
+        int rc = upload(c, &c->d_pairs, pairs);
+        if (rc == TDKS_OK) rc = upload(c, &c->d_pair_first, first);
+        if (rc == TDKS_OK) {
+            c->d_rho_k = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * pairs.size()));
+            c->d_rho_in = static_cast<double *>(c->alloc(sizeof(double) * size_t(c->ng_max) * c->n_inst));
+            c->d_resid = static_cast<double *>(c->alloc(sizeof(double) * c->n_inst));
+            c->d_status = static_cast<int *>(c->alloc(sizeof(int)));
+            if (!c->d_rho_in || !c->d_resid || !c->d_status || !c->d_rho_k)
+                rc = fail(TDKS_E_OOM, "ground-state buffers (%zu bytes of density partials)",
+                          sizeof(double) * size_t(c->ng_max) * pairs.size());
+        }
+        if (rc != TDKS_OK) {
+            drop();
+            return rc;
+        }
+        c->n_pairs = int(pairs.size());
     }
     const bool scf = (c->opt.hxc_mode == TDKS_HXC_SCF);
     int nb_max = 1;
