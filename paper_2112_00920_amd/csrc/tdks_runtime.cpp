@@ -612,13 +612,19 @@ int ensure_A(tdks_ctx *c, size_t n) {
     if (n <= c->A_cap) return TDKS_OK;
     HIPCHK(hipStreamSynchronize(c->stream));
     size_t cap = std::max<size_t>(n, std::max<size_t>(2 * c->A_cap, 1024));
+    // both new buffers first: on failure the old pair stays in place, consistent with A_cap
+    double *hn = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&hn), sizeof(double) * 6 * cap, hipHostMallocDefault) != hipSuccess)
+        return fail(TDKS_E_OOM, "pinned A table allocation failed");
     double *na = static_cast<double *>(c->alloc(sizeof(double) * 6 * cap));
-    if (!na) return fail(TDKS_E_OOM, "A table allocation failed");
+    if (!na) {
+        (void)hipHostFree(hn);
+        return fail(TDKS_E_OOM, "A table allocation failed");
+    }
     c->release(c->d_A);
     c->d_A = na;
     if (c->h_A) (void)hipHostFree(c->h_A);
-    c->h_A = nullptr;
-    HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c->h_A), sizeof(double) * 6 * cap, hipHostMallocDefault));
+    c->h_A = hn;
     c->A_cap = cap;
     c->drop_graphs();
     return TDKS_OK;
