@@ -114,6 +114,11 @@ struct tdks_ctx {
     hipStream_t stream = nullptr;
     hipStream_t caller = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_acopy = nullptr;
+    // with several shape classes: side streams (default priority) that the classes after the
+    // first run on, forked from and joined back to `stream` every time
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
     // device buffers
     DevInst *d_insts = nullptr;
     WorkItem *d_work = nullptr;
@@ -526,15 +531,36 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     return a;
 }
 
-// the propagation launches of one step of every instance (mode STEP or PREDICT)
-int enqueue_propagation(tdks_ctx *c, int mode) {
-    for (const ShapeClass &S : c->classes) {
-        PropArgs a = class_args(c, S, mode, c->d_A, c->d_ctrs);
-        a.work = c->d_work + S.wbeg;
-        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
-                                c->stream));
+// Runs launch(S, stream) for every shape class.  With several classes, the first stays on the
+// context's stream and the others go to the side streams, forked from it and joined back, so
+// that the last workgroups of one class overlap another class instead of leaving compute
+// units idle (the classes touch disjoint instances).  Graph-capturable: the fork and join
+// become parallel branches of the graph.
+template <typename F>
+int for_classes(tdks_ctx *c, F &&launch) {
+    const int nc = int(c->classes.size()), ns = int(c->side.size());
+    if (nc <= 1 || ns == 0) {
+        for (const ShapeClass &S : c->classes) CHK(launch(S, c->stream));
+        return TDKS_OK;
+    }
+    HIPCHK(hipEventRecord(c->ev_fork, c->stream));
+    for (int q = 0; q < ns; ++q) HIPCHK(hipStreamWaitEvent(c->side[q], c->ev_fork, 0));
+    for (int s = 0; s < nc; ++s) CHK(launch(c->classes[s], s == 0 ? c->stream : c->side[(s - 1) % ns]));
+    for (int q = 0; q < ns; ++q) {
+        HIPCHK(hipEventRecord(c->ev_join[q], c->side[q]));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[q], 0));
     }
     return TDKS_OK;
+}
+
+// the propagation launches of one step of every instance (mode STEP or PREDICT)
+int enqueue_propagation(tdks_ctx *c, int mode) {
+    return for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
+        PropArgs a = class_args(c, S, mode, c->d_A, c->d_ctrs);
+        a.work = c->d_work + S.wbeg;
+        HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
+        return TDKS_OK;
+    });
 }
 
 bool predictor_corrector(const tdks_ctx *c) {
@@ -643,7 +669,7 @@ size_t orb_bytes(const tdks_ctx *c, const InstHost &I) {
 // observe: current (and density) of instance range for given A; writes d_jobs or d_jpre.
 // enqueue_observe leaves the work on the stream; d_Aobs must already hold A.
 int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int mode = MODE_OBSERVE) {
-    for (const ShapeClass &S : c->classes) {
+    CHK(for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
         int wb = S.wend, we = S.wbeg;
         for (int i = i_first; i <= i_last; ++i) {
             const InstHost &I = c->inst[i];
@@ -651,12 +677,12 @@ int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int mode
             wb = std::min(wb, I.wbeg);
             we = std::max(we, I.wend);
         }
-        if (we <= wb) continue;
+        if (we <= wb) return TDKS_OK;
         PropArgs a = class_args(c, S, mode, c->d_Aobs, c->d_ctrs + 2);
         a.work = c->d_work + wb;
-        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
-                                c->stream));
-    }
+        HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
+        return TDKS_OK;
+    }));
     HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
                          c->stream));
     return TDKS_OK;
@@ -718,6 +744,12 @@ void tdks_destroy(tdks_ctx *c) {
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->ev_acopy) (void)hipEventDestroy(c->ev_acopy);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (hipEvent_t e : c->ev_join) (void)hipEventDestroy(e);
+    for (hipStream_t st : c->side) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -879,6 +911,18 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_acopy, hipEventDisableTiming));
+    // side streams for the shape classes after the first (at most 3: with the context's own
+    // stream, the 4 hardware queues a process gets by default)
+    const int n_side = std::min(int(c->classes.size()) - 1, 3);
+    for (int q = 0; q < n_side; ++q) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->side.push_back(st);
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->ev_join.push_back(ev);
+    }
+    if (n_side > 0) HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     for (TableSet &T : c->tables) {
         CHK(upload(c, &T.d_col_atom, T.col_atom));
         CHK(upload(c, &T.d_col_j01, T.col_j01));
@@ -1147,13 +1191,14 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
     HIPCHK(hipMemcpyAsync(c->d_rho_in, c->d_rho, sizeof(double) * size_t(c->ng_max) * c->n_inst,
                           hipMemcpyDeviceToDevice, c->stream));
     for (int it = 0; it < n_iter; ++it) {
-        for (const ShapeClass &S : c->classes) {
+        CHK(for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
             PropArgs a = class_args(c, S, MODE_ITIME, c->d_Aobs, c->d_ctrs + 2);
             a.dt = tau;
             a.work = c->d_work + S.wbeg;
             HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
-                                    c->stream));
-        }
+                                    st));
+            return TDKS_OK;
+        }));
         HIPCHK(launch_orth(c->d_insts, c->d_pairs, c->n_pairs, nb_max, c->fp64, c->d_status, c->d_rho_k, c->ng_max,
                            c->stream));
         HIPCHK(launch_reduce_k(c->d_insts, c->n_inst, c->d_pair_first, c->d_rho_k, c->ng_max, c->d_rho, c->stream));
