@@ -97,10 +97,10 @@ hipError_t launch_reduce_k(const DevInst *insts, int n_inst, const int *first, c
 
 // ---------------------------------------------------------------------------
 // Hartree + LDA, one workgroup per instance.  Poisson: rho(G) by a separable
-// discrete Fourier transform (each line of N_d <= 32 points held in registers,
-// twiddles from sincospi), v_H(G) = 4 pi rho(G) / |G|^2 with G = 0 and the
-// Nyquist planes zeroed, inverse transform.  Exchange: Slater; correlation:
-// Perdew-Zunger 81 (unpolarised).
+// discrete Fourier transform (each line of N_d <= 32 points held in registers, each
+// output by Horner's rule in its twiddle, twiddles from sincospi), v_H(G) =
+// 4 pi rho(G) / |G|^2 with G = 0 and the Nyquist planes zeroed, inverse transform.
+// Exchange: Slater; correlation: Perdew-Zunger 81 (unpolarised).
 __device__ double lda_vxc(double rho) {
     if (!(rho > 1e-30)) return 0.0;
     const double pi = 3.141592653589793;
@@ -129,27 +129,36 @@ __device__ void dft_pass(double2 *X, const double2 *tw, int n, int stride, int n
 #pragma unroll
         for (int i = 0; i < kMaxGridDim; ++i)
             if (i < n) line[i] = X[start + i * stride];
-        for (int m = 0; m < n; ++m) {
-            double sx = 0.0, sy = 0.0;
-            int q = 0;
+        // X_m = sum_i x_i z^i with z = e^{-+2 pi i m / n}, by Horner's rule (|z| = 1: the
+        // rounding stays at the direct sum's level; one twiddle read per output), two outputs
+        // at a time so that their chains of multiply-adds overlap
+        for (int m = 0; m < n; m += 2) {
+            const int m1 = (m + 1 < n) ? m + 1 : m;
+            const double2 t0 = tw[m], t1 = tw[m1];
+            const double z0x = t0.x, z0y = inverse ? -t0.y : t0.y;
+            const double z1x = t1.x, z1y = inverse ? -t1.y : t1.y;
+            double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
 #pragma unroll
-            for (int i = 0; i < kMaxGridDim; ++i) {
+            for (int i = kMaxGridDim - 1; i >= 0; --i) {
                 if (i < n) {
-                    double2 t = tw[q];
-                    double ty = inverse ? -t.y : t.y;
-                    sx += line[i].x * t.x - line[i].y * ty;
-                    sy += line[i].x * ty + line[i].y * t.x;
-                    q += m;
-                    if (q >= n) q -= n;
+                    const double a0 = fma(s0x, z0x, fma(-s0y, z0y, line[i].x));
+                    s0y = fma(s0x, z0y, fma(s0y, z0x, line[i].y));
+                    s0x = a0;
+                    const double a1 = fma(s1x, z1x, fma(-s1y, z1y, line[i].x));
+                    s1y = fma(s1x, z1y, fma(s1y, z1x, line[i].y));
+                    s1x = a1;
                 }
             }
-            X[start + m * stride] = make_double2(sx, sy);
+            X[start + m * stride] = make_double2(s0x, s0y);
+            if (m + 1 < n) X[start + m1 * stride] = make_double2(s1x, s1y);
         }
     }
 }
 
+constexpr int kHxcThreads = 512;  // 2 waves per SIMD: a line of 32 points stays in registers
+
 template <typename R>
-__global__ __launch_bounds__(256) void k_hxc(const DevInst *insts, int inst0, int ng_max,
+__global__ __launch_bounds__(kHxcThreads) void k_hxc(const DevInst *insts, int inst0, int ng_max,
                                              const double *rho, const double *vloc, double *vhxc,
                                              R *vtot) {
     extern __shared__ __align__(16) char smem[];
@@ -221,13 +230,13 @@ hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const 
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_hxc<double>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_hxc<double>, dim3(n), dim3(256), lds, s, insts, inst0, ng_max, rho,
+        hipLaunchKernelGGL(k_hxc<double>, dim3(n), dim3(kHxcThreads), lds, s, insts, inst0, ng_max, rho,
                            vloc, vhxc, reinterpret_cast<double *>(vtot));
     } else {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_hxc<float>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_hxc<float>, dim3(n), dim3(256), lds, s, insts, inst0, ng_max, rho,
+        hipLaunchKernelGGL(k_hxc<float>, dim3(n), dim3(kHxcThreads), lds, s, insts, inst0, ng_max, rho,
                            vloc, vhxc, reinterpret_cast<float *>(vtot));
     }
     return hipGetLastError();
