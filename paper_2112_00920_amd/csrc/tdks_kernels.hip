@@ -45,30 +45,48 @@ hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block,
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic FP64 reduction of the per-workgroup partials (fixed slot order).
+// Deterministic FP64 reduction of the per-workgroup partials (a fixed order, independent of
+// timing).  Density: 64 points per workgroup; wave w sums the slots w, w + 4, ... of each
+// point (coalesced rows) and the four wave sums are added in wave order.  Current (the
+// first workgroup of the instance): lane l sums the slots l, l + 64, ..., then a fixed
+// butterfly over the wave.
 __global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0, int ng_max,
                                                 double *rho, double *jout, int jstride,
                                                 const int *rec_ctr) {
+    __shared__ double part[3][64];
     const int inst = inst0 + blockIdx.y;
     const DevInst &I = insts[inst];
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p < I.ng) {
-        double s = 0.0;
-        for (int q = 0; q < I.nslot; ++q) s += I.rho_part[size_t(q) * I.ng + p];
-        rho[size_t(inst) * ng_max + p] = s;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < 3) {
-        double s = 0.0;
-        for (int q = 0; q < I.nslot; ++q) s += I.j_part[4 * q + threadIdx.x];
-        const int rec = rec_ctr ? *rec_ctr : 0;
-        jout[(size_t(inst) * jstride + rec) * 3 + threadIdx.x] = -s / I.omega;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (p < I.ng)
+        for (int q = w; q < I.nslot; q += 4) s += I.rho_part[size_t(q) * I.ng + p];
+    if (w > 0) part[w - 1][lane] = s;
+    __syncthreads();
+    if (w == 0 && p < I.ng)
+        rho[size_t(inst) * ng_max + p] = ((s + part[0][lane]) + part[1][lane]) + part[2][lane];
+    if (blockIdx.x == 0 && w == 1) {
+        double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+        for (int q = lane; q < I.nslot; q += 64) {
+            j0 += I.j_part[4 * q];
+            j1 += I.j_part[4 * q + 1];
+            j2 += I.j_part[4 * q + 2];
+        }
+        j0 = wave_sum(j0);
+        j1 = wave_sum(j1);
+        j2 = wave_sum(j2);
+        if (lane < 3) {
+            const int rec = rec_ctr ? *rec_ctr : 0;
+            const double j = lane == 0 ? j0 : lane == 1 ? j1 : j2;
+            jout[(size_t(inst) * jstride + rec) * 3 + lane] = -j / I.omega;
+        }
     }
 }
 
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
                          double *jout, int jstride, const int *rec_ctr, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    dim3 grid((ng_max + 255) / 256, n);
+    dim3 grid((ng_max + 63) / 64, n);
     hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, insts, inst0, ng_max, rho, jout, jstride,
                        rec_ctr);
     return hipGetLastError();
