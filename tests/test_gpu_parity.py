@@ -296,3 +296,29 @@ def test_eigenstate_norm_closed_form_on_gpu(tdks):
     for j, s in enumerate(sel):
         x = e[s] * dt
         assert abs(nr[j] - (1 - x ** 6 / 72 + x ** 8 / 576) ** n) < 1e-12
+
+
+def test_concurrent_classes_graph_equals_eager(tdks):
+    """Four shape classes, whose launches run concurrently on forked streams: 18 steps through
+    16-step graphs (fork and join captured as parallel branches) against eager launches, bitwise
+    (the classes write disjoint data, so their overlap cannot change a bit)."""
+    _say("concurrent shape classes: graph vs eager")
+    sp = species(6)
+    insts = [
+        W.make_instance("fcc2", (8, 8, 8), 3, [sp], W.KSpec((2, 1, 1)), group=0),
+        W.make_instance("diamond8", (8, 8, 8), 4, [sp], W.KSpec((2, 1, 1)), group=1),
+        W.make_instance("diamond8", (10, 10, 10), 3, [sp], W.KSpec((1, 1, 1)), group=1),
+        W.make_instance("super16", (8, 8, 16), 4, [sp], W.KSpec((1, 1, 2)), group=2),
+    ]
+    u0s = [W.random_orbitals(60 + i, inst.n_k, inst.n_bands, inst.grid, inst.omega) for i, inst in enumerate(insts)]
+    A = W.Field("kick", 1e-3).table(18, 0.02)
+    out = {}
+    for gs in (16, -1):
+        with tdks.Propagator(insts, precision="fp32", graph_steps=gs) as prop:
+            for i, u in enumerate(u0s):
+                prop.load_orbitals(i, u)
+            prop.step(A)
+            out[gs] = (prop.current(), [prop.get_orbitals(i) for i in range(len(insts))])
+    for i in range(len(insts)):
+        assert np.array_equal(out[16][0][i], out[-1][0][i]), i
+        assert np.array_equal(out[16][1][i], out[-1][1][i]), i
