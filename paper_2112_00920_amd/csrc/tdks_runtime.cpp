@@ -119,6 +119,7 @@ struct tdks_ctx {
     std::vector<hipStream_t> side;
     std::vector<hipEvent_t> ev_join;
     hipEvent_t ev_fork = nullptr;
+    std::vector<int> class_order;  // launch order: the class with the longest work items first
     // device buffers
     DevInst *d_insts = nullptr;
     WorkItem *d_work = nullptr;
@@ -545,7 +546,8 @@ int for_classes(tdks_ctx *c, F &&launch) {
     }
     HIPCHK(hipEventRecord(c->ev_fork, c->stream));
     for (int q = 0; q < ns; ++q) HIPCHK(hipStreamWaitEvent(c->side[q], c->ev_fork, 0));
-    for (int s = 0; s < nc; ++s) CHK(launch(c->classes[s], s == 0 ? c->stream : c->side[(s - 1) % ns]));
+    for (int r = 0; r < nc; ++r)
+        CHK(launch(c->classes[c->class_order[r]], r == 0 ? c->stream : c->side[(r - 1) % ns]));
     for (int q = 0; q < ns; ++q) {
         HIPCHK(hipEventRecord(c->ev_join[q], c->side[q]));
         HIPCHK(hipStreamWaitEvent(c->stream, c->ev_join[q], 0));
@@ -901,6 +903,19 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
             I.nslot = slot;
         }
         S.wend = int(c->work.size());
+    }
+    // classes in decreasing work per item (grid points x k-points x bands of its largest item),
+    // so that the longest workgroups start first and do not end up as a step's tail
+    {
+        std::vector<double> cost(c->classes.size(), 0.0);
+        for (const WorkItem &w : c->work) {
+            const InstHost &I = c->inst[w.inst];
+            cost[I.cls] = std::max(cost[I.cls], double(I.ng) * w.nk * w.nb);
+        }
+        c->class_order.resize(c->classes.size());
+        for (size_t s = 0; s < c->classes.size(); ++s) c->class_order[s] = int(s);
+        std::stable_sort(c->class_order.begin(), c->class_order.end(),
+                         [&](int x, int y) { return cost[x] > cost[y]; });
     }
     for (const InstHost &I : c->inst) {
         if (std::find(c->groups.begin(), c->groups.end(), I.group) == c->groups.end()) c->groups.push_back(I.group);
