@@ -93,8 +93,7 @@ def test_two_step_equals_dense_with_frozen_hxc():
     A = np.array([[[-1e-3, 0, 0], [-1e-3, 0, 0]]] * 3)
     rd = P.Run(dense, u_dense, 0.02, "frozen", v_frozen)
     Jd = rd.run(A)
-    Jsum = np.zeros_like(Jd)
-    Jpre = np.zeros(3)
+    per_shift, pre_shift = [], []
     seen = 0
     for j3 in range(2):
         for j2 in range(2):
@@ -103,10 +102,14 @@ def test_two_step_equals_dense_with_frozen_hxc():
                 # locate each shifted k in the dense list (exact binary equality)
                 idx = [int(np.nonzero(np.all(dense.k_frac == kk, axis=1))[0][0]) for kk in sub.k_frac]
                 rs = P.Run(sub, u_dense[idx], 0.02, "frozen", v_frozen)
-                Jsum += rs.run(A)
-                Jpre += rs.J_pre
+                per_shift.append(rs.run(A))
+                pre_shift.append(rs.J_pre)
                 assert np.array_equal(rs.u, rd.u[idx])
                 seen += len(idx)
     assert seen == n_dense
-    np.testing.assert_allclose(Jsum / 8, Jd, rtol=1e-14, atol=1e-19)
-    np.testing.assert_allclose(Jpre / 8, rd.J_pre, rtol=1e-14, atol=1e-19)
+    # Eq. (9): the plain mean over the N_H = 8 sub-simulations equals the direct 4^3 run
+    np.testing.assert_allclose(P.two_step_average(per_shift), Jd, rtol=1e-14, atol=1e-19)
+    np.testing.assert_allclose(P.two_step_average(pre_shift), rd.J_pre, rtol=1e-14, atol=1e-19)
+    # and it is the mean of the induced currents too (delta J_m = J_m - J_m^pre, per shift)
+    dj = [j - p for j, p in zip(per_shift, pre_shift)]
+    np.testing.assert_allclose(P.two_step_average(dj), Jd - rd.J_pre, rtol=1e-12, atol=1e-19)
