@@ -59,7 +59,7 @@ extern "C" {
 #define TDKS_E_OOM (-2)         /* device allocation failed                   */
 #define TDKS_E_HIP (-3)         /* HIP runtime error                          */
 #define TDKS_E_STATE (-4)       /* call not valid in the context's state      */
-#define TDKS_E_NUMERIC (-5)     /* non-finite current detected                */
+#define TDKS_E_NUMERIC (-5)     /* numeric health check failed (tdks_check)    */
 #define TDKS_E_UNSUPPORTED (-6) /* size or option outside the built kernels   */
 
 /* precision of the propagation arithmetic */
@@ -135,6 +135,9 @@ typedef struct tdks_options {
     int waves_per_simd;   /* occupancy target of the propagation kernel: 2 or 4
                              (0 = automatic); selects the register budget          */
     int propagator;       /* TDKS_PROP_TAYLOR (default) or TDKS_PROP_PC            */
+    int norm_stride;      /* per-orbital norm check every norm_stride steps (0 = off;
+                             the charge is checked every step regardless)          */
+    int record_stride;    /* record the current every record_stride-th step (0 = 1) */
 } tdks_options;
 
 typedef struct tdks_ctx tdks_ctx;
@@ -171,6 +174,18 @@ const char *tdks_last_error(void);
  * Errors: E_ARG, E_HIP. */
 int tdks_load_orbitals(tdks_ctx *ctx, int inst, const void *u, int where);
 
+/* Numeric health check (checked on the device inside every step, no host work).  The
+ * Taylor-4 step multiplies the squared norm of each eigencomponent of the Hermitian h_kappa by
+ * |T4(-i x)|^2 = 1 - x^6/72 + x^8/576, x = dt lambda (Eq. 1 expanded to 4th order): <= 1 for
+ * |x| <= 2 sqrt 2, decreasing in |x| below sqrt 6.  Every step checks, per instance, that the
+ * current J^{n+1} (Eq. 5) and the charge Q = sum_k w_k sum_b f_b ||u_bk||^2 (the integral of
+ * Eq. 3) are finite and that Q0 F_1 ... F_n (1 - tol) <= Q <= Q0 (1 + tol), Q0 = Q at the load,
+ * F_m = that factor at x = |dt| lambda_max(A(t_m + dt/2)) with lambda_max a bound of |lambda|
+ * (kinetic bound at kappa = k + A, |v_loc|, the KB operator norms, and 5 Ha for |v_Hxc|);
+ * tol = 1e-9 (FP64) or 1e-4 (FP32_MIXED).  With norm_stride > 0 every norm_stride-th step also
+ * checks each orbital's norm against the same bounds times its norm at the load.  The first
+ * violation of each instance is recorded on the device. */
+
 /* Advances every instance by n_steps Taylor-4 steps (Eq. 1) under the uniform
  * vector potential table A_tab (HOST, [n_steps][2][3]: A(t_n + dt/2) used in
  * h for step n, and A(t_{n+1}) used for the current recorded after it).
@@ -180,13 +195,27 @@ int tdks_load_orbitals(tdks_ctx *ctx, int inst, const void *u, int where);
  * (v_Hxc[rho(t_n)] + v~) / 2; twice the propagation work, and the Hxc coupling
  * becomes second order in dt.  With frozen or no Hxc the two propagators are
  * the same step.  The
- * current J^{n+1} (Eq. 5) of every instance is recorded after every step.
- * Enqueued asynchronously (HIP graphs of opt->graph_steps steps); the host
- * does no per-step work.  Errors: E_STATE (an instance not loaded), E_ARG,
- * E_OOM (trace growth), E_HIP. */
+ * current J^{n+1} (Eq. 5) of every instance is recorded after every
+ * record_stride-th step.  Enqueued asynchronously (HIP graphs of opt->graph_steps
+ * steps); the host does no per-step work.  The health record is copied to the host
+ * asynchronously at the end of the call.  Errors: E_STATE (an instance not loaded),
+ * E_ARG, E_OOM (trace growth), E_HIP, E_NUMERIC (the health record of an earlier
+ * call had arrived by the start of this one and shows a violation: nothing is
+ * enqueued; the message names the instance, the step and the check). */
 int tdks_step(tdks_ctx *ctx, int n_steps, const double *A_tab);
 
-/* Number of steps recorded since the last load (a load resets the record). */
+/* Waits for the context's work and returns E_NUMERIC if any instance failed the health
+ * check since its load (the message names the first such instance, the step counted from
+ * the load, the check, and for an orbital check its k and band), else TDKS_OK.  info
+ * (HOST [n_inst], may be NULL) receives each instance's record: 0 = healthy, else
+ * step << 32 | (k n_bands + band + 1) << 4 | code (orbital field 0 for the charge checks;
+ * code 1 non-finite current or charge, 2 / 3 charge above / below its bounds, 4 / 5 an
+ * orbital norm above / below them).  A load or tdks_ground_state clears the records of
+ * the instances it sets.  Errors: E_ARG, E_HIP, E_NUMERIC. */
+int tdks_check(tdks_ctx *ctx, unsigned long long *info);
+
+/* Number of steps taken since the last load (a load resets it); the current is
+ * recorded for steps_done / record_stride of them. */
 int tdks_steps_done(tdks_ctx *ctx);
 
 /* Ground-state preparation (the runs of Sec. III start from the Kohn-Sham
@@ -220,13 +249,14 @@ int tdks_steps_done(tdks_ctx *ctx);
  * that k are left unchanged), E_OOM, E_HIP. */
 int tdks_ground_state(tdks_ctx *ctx, int n_iter, double tau, double mix, double *residual);
 
-/* Copies the induced current delta J^n = J^n - J_pre for n = 1..steps_done
- * into out (HOST).  mode TDKS_PER_INSTANCE: [n_inst][steps][3];
- * TDKS_PER_GROUP: [n_groups][steps][3], the plain mean over the instances of
- * each group in ascending group id (Eq. 9 / procedure step 4).  cap is the
- * capacity of out in doubles; *n_written receives the number written.
- * Synchronises.  Errors: E_ARG (cap too small), E_NUMERIC (a non-finite value;
- * the message names the instance), E_HIP. */
+/* Copies the induced current delta J^n = J^n - J_pre for n = s, 2s, ..., R s
+ * (s = record_stride, R = steps_done / s) into out (HOST).  mode TDKS_PER_INSTANCE:
+ * [n_inst][R][3]; TDKS_PER_GROUP: [n_groups][R][3], the plain mean over the
+ * instances of each group in ascending group id (Eq. 9 / procedure step 4).  cap
+ * is the capacity of out in doubles; *n_written receives the number written.
+ * Synchronises.  Errors: E_ARG (cap too small), E_NUMERIC (the health check of
+ * tdks_check failed, or a non-finite value; the message names the instance),
+ * E_HIP. */
 int tdks_current(tdks_ctx *ctx, int mode, double *out, size_t cap, size_t *n_written);
 
 /* J_pre of every instance, HOST out[n_inst][3].  Synchronises. */

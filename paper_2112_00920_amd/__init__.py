@@ -74,7 +74,7 @@ class Propagator:
                  dt: float = 0.02, hxc_mode: str = "scf", v_hxc_frozen: Optional[Sequence] = None,
                  bands_per_group: int = 0, k_per_group: int = 0, block_size: int = 0,
                  graph_steps: int = 16, waves_per_simd: int = 0, use_torch: bool = True,
-                 propagator: str = "taylor"):
+                 propagator: str = "taylor", norm_stride: int = 0, record_stride: int = 1):
         self._lib = _lib.load()
         self._ctx = None
         self.n_inst = len(instances)
@@ -122,6 +122,9 @@ class Propagator:
         opt.graph_steps = int(graph_steps)
         opt.propagator = {"taylor": _lib.PROP_TAYLOR, "pc": _lib.PROP_PC}[propagator]
         opt.waves_per_simd = int(waves_per_simd)
+        opt.norm_stride = int(norm_stride)
+        opt.record_stride = int(record_stride)
+        self.record_stride = max(1, int(record_stride))
         self._alloc = None
         self._torch = None
         if use_torch:
@@ -200,8 +203,20 @@ class Propagator:
     def steps_done(self) -> int:
         return int(self._lib.tdks_steps_done(self._ctx))
 
+    def check(self) -> np.ndarray:
+        """Health records of every instance (tdks_check; raises TdksError E_NUMERIC on a
+        violation, with the records in the exception's `info`)."""
+        info = (ctypes.c_ulonglong * self.n_inst)()
+        rc = self._lib.tdks_check(self._ctx, info)
+        rec = np.array(list(info), dtype=np.uint64)
+        if rc != _lib.TDKS_OK:
+            err = TdksError(rc, self._lib.tdks_last_error().decode(errors="replace"))
+            err.info = rec
+            raise err
+        return rec
+
     def current(self, per: str = "instance") -> np.ndarray:
-        ns = self.steps_done
+        ns = self.steps_done // self.record_stride
         mode = _lib.PER_GROUP if per == "group" else _lib.PER_INSTANCE
         rows = len(set(a["group"] for a in self.arrays)) if per == "group" else self.n_inst
         out = np.zeros((rows, ns, 3))

@@ -62,6 +62,8 @@ class Options(ctypes.Structure):
         ("graph_steps", ctypes.c_int),
         ("waves_per_simd", ctypes.c_int),
         ("propagator", ctypes.c_int),
+        ("norm_stride", ctypes.c_int),
+        ("record_stride", ctypes.c_int),
     ]
 
 
@@ -74,6 +76,7 @@ SYMBOLS = {
     "tdks_load_orbitals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
     "tdks_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p]),
     "tdks_steps_done": (ctypes.c_int, [ctypes.c_void_p]),
+    "tdks_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]),
     "tdks_ground_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_void_p]),
     "tdks_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, ctypes.c_size_t,

@@ -56,9 +56,31 @@ struct DevInst {
     const double *atom_par;    // [nat][4] Es, Ep, Ns, Np
     // per-step outputs of the propagation kernel
     double *rho_part;   // [nslot][ng] partial densities (one slot per work item)
-    double *j_part;     // [nslot][4] partial currents
+    double *j_part;     // [nslot][4] partial currents (x, y, z) and charge sum_k w_k sum_b f_b ||u||^2
     int nslot;
     int pad_;
+    double *norm0;      // [nk][nb] norms at load (per-orbital health check), or null
+};
+
+// Numeric health check of a step (per instance).  The charge Q = sum_k w_k sum_b f_b ||u_bk||^2
+// is summed with the current every step; the Taylor-4 step multiplies the squared norm of an
+// eigencomponent of the (Hermitian) h by |T4(-i x)|^2 = 1 - x^6/72 + x^8/576, x = dt lambda,
+// which is <= 1 for |x| <= 2 sqrt 2 and, below sqrt 6, decreasing in |x|.  With a bound
+// lambda_max of |lambda| a step therefore keeps Q within [Q F, Q], F = |T4(-i dt lambda_max)|^2
+// (0.25 beyond sqrt 6).  logF holds log F per step (A-table row), lcum its running sum since the
+// load.  A violation records (step << 32) | (orbital + 1) << 4 | code in health[inst] (first
+// one only): code 1 non-finite current or charge, 2 charge above Q0 (1 + tol), 3 charge below
+// Q0 (e^lcum - tol), 4 / 5 an orbital's norm above / below the same bounds.
+struct HealthArgs {
+    double *q0;                     // [n_inst] charge at load (written when set_ref)
+    double *lcum;                   // [n_inst] accumulated log F since load
+    const double *logF;             // [A rows] log F of each step, or null (no lower bound)
+    const int *arow;                // A-table row of the step
+    unsigned long long *health;     // [n_inst] first violation, 0 if none (null: no check)
+    const int *row_ctr;             // record row of every step instead (or null)
+    int set_ref;                    // observe: store Q as Q0 and reset lcum
+    int rstride;                    // record every rstride-th current
+    double tol;                     // relative tolerance (rounding of the propagation precision)
 };
 
 // One workgroup's share: bands [b0, b0+nb) of k-points [k0, k0+nk) of an instance.
@@ -108,7 +130,9 @@ hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block,
 size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block);
 bool propagate_config_ok(int block, int zl, int minw, int ragged);
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
-                         double *jout, int jstride, const int *rec_ctr, hipStream_t s);
+                         double *jout, int jstride, const int *step_ctr, const HealthArgs &h, hipStream_t s);
+hipError_t launch_health_norms(const DevInst *insts, const WorkItem *work, int n_items, const int *step_ctr,
+                               int stride, const HealthArgs &h, int fp64, hipStream_t s);
 hipError_t launch_hxc(const DevInst *insts, int inst0, int n, int ng_max, const double *rho,
                       const double *vloc, double *vhxc, void *vtot, int fp64, hipStream_t s);
 hipError_t launch_vtot(const DevInst *insts, int inst0, int n, int ng_max, const double *vloc,

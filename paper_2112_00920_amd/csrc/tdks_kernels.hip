@@ -47,12 +47,15 @@ hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block,
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reduction of the per-workgroup partials (a fixed order, independent of
 // timing).  Density: 64 points per workgroup; wave w sums the slots w, w + 4, ... of each
-// point (coalesced rows) and the four wave sums are added in wave order.  Current (the
-// first workgroup of the instance): lane l sums the slots l, l + 64, ..., then a fixed
-// butterfly over the wave.
+// point (coalesced rows) and the four wave sums are added in wave order.  Current and charge
+// (the first workgroup of the instance): lane l sums the slots l, l + 64, ..., then a fixed
+// butterfly over the wave.  After a step (step_ctr given: steps since the load before this
+// one) the current J^{n} is recorded at row n / rstride - 1 when rstride divides n, and the
+// charge is checked against the bounds of HealthArgs; an observation (step_ctr null) writes
+// row 0 and, with set_ref, takes the charge as the instance's reference.
 __global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0, int ng_max,
                                                 double *rho, double *jout, int jstride,
-                                                const int *rec_ctr) {
+                                                const int *step_ctr, HealthArgs h) {
     __shared__ double part[3][64];
     const int inst = inst0 + blockIdx.y;
     const DevInst &I = insts[inst];
@@ -66,29 +69,103 @@ __global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0,
     if (w == 0 && p < I.ng)
         rho[size_t(inst) * ng_max + p] = ((s + part[0][lane]) + part[1][lane]) + part[2][lane];
     if (blockIdx.x == 0 && w == 1) {
-        double j0 = 0.0, j1 = 0.0, j2 = 0.0;
-        for (int q = lane; q < I.nslot; q += 64) {
-            j0 += I.j_part[4 * q];
-            j1 += I.j_part[4 * q + 1];
-            j2 += I.j_part[4 * q + 2];
+        double j0 = 0.0, j1 = 0.0, j2 = 0.0, q = 0.0;
+        for (int t = lane; t < I.nslot; t += 64) {
+            j0 += I.j_part[4 * t];
+            j1 += I.j_part[4 * t + 1];
+            j2 += I.j_part[4 * t + 2];
+            q += I.j_part[4 * t + 3];
         }
         j0 = wave_sum(j0);
         j1 = wave_sum(j1);
         j2 = wave_sum(j2);
-        if (lane < 3) {
-            const int rec = rec_ctr ? *rec_ctr : 0;
+        q = wave_sum(q);
+        const int n = step_ctr ? *step_ctr + 1 : 0;  // steps since the load after this one
+        const int rs = h.rstride > 0 ? h.rstride : 1;
+        if (lane < 3 && (!step_ctr || h.row_ctr || n % rs == 0)) {
+            const int row = h.row_ctr ? *h.row_ctr : step_ctr ? n / rs - 1 : 0;
             const double j = lane == 0 ? j0 : lane == 1 ? j1 : j2;
-            jout[(size_t(inst) * jstride + rec) * 3 + lane] = -j / I.omega;
+            jout[(size_t(inst) * jstride + row) * 3 + lane] = -j / I.omega;
+        }
+        if (lane == 0 && h.set_ref && h.q0) {
+            h.q0[inst] = q;
+            h.lcum[inst] = 0.0;
+        }
+        if (lane == 0 && step_ctr && h.health) {
+            const double lc = h.lcum[inst] + (h.logF ? h.logF[*h.arow] : 0.0);
+            h.lcum[inst] = lc;
+            const double q0 = h.q0[inst];
+            int code = 0;
+            if (!(isfinite(j0) && isfinite(j1) && isfinite(j2) && isfinite(q)))
+                code = 1;
+            else if (q > q0 * (1.0 + h.tol))
+                code = 2;
+            else if (h.logF && q < q0 * (exp(lc) - h.tol))
+                code = 3;
+            if (code)
+                atomicCAS(h.health + inst, 0ull, (static_cast<unsigned long long>(n) << 32) | unsigned(code));
         }
     }
 }
 
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
-                         double *jout, int jstride, const int *rec_ctr, hipStream_t s) {
+                         double *jout, int jstride, const int *step_ctr, const HealthArgs &h, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     dim3 grid((ng_max + 63) / 64, n);
     hipLaunchKernelGGL(k_reduce, grid, dim3(256), 0, s, insts, inst0, ng_max, rho, jout, jstride,
-                       rec_ctr);
+                       step_ctr, h);
+    return hipGetLastError();
+}
+
+// Per-orbital part of the health check, every `stride` steps (the step counter is read on the
+// device, so the launch sits in every captured step and returns at once when not due): one
+// workgroup per work item, each wave sums sum_r |u|^2 dV of one orbital at a time in FP64 and
+// compares it with the orbital's norm at the load times the bounds of the charge check.
+template <typename C>
+__global__ __launch_bounds__(256) void k_health_norms(const DevInst *insts, const WorkItem *work,
+                                                      const int *step_ctr, int stride, HealthArgs h) {
+    const int n = *step_ctr + 1;
+    if (n % stride) return;
+    const WorkItem wi = work[blockIdx.x];
+    const DevInst &I = insts[wi.inst];
+    if (!I.norm0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double lc = h.lcum[wi.inst] + (h.logF ? h.logF[*h.arow] : 0.0);
+    const int norb = wi.nk * wi.nb;
+    for (int o = wave; o < norb; o += 4) {
+        const int k = wi.k0 + o / wi.nb, b = wi.b0 + o % wi.nb;
+        const size_t orb = size_t(k) * I.nb + b;
+        const C *u = reinterpret_cast<const C *>(I.u) + orb * I.ng;
+        double sq = 0.0;
+        for (int p = lane; p < I.ng; p += 64) {
+            const C v = u[p];
+            sq += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+        }
+        sq = wave_sum(sq) * I.dV;
+        if (lane == 0) {
+            const double n0 = I.norm0[orb];
+            int code = 0;
+            if (!isfinite(sq))
+                code = 1;
+            else if (sq > n0 * (1.0 + h.tol))
+                code = 4;
+            else if (h.logF && sq < n0 * (exp(lc) - h.tol))
+                code = 5;
+            if (code)
+                atomicCAS(h.health + wi.inst, 0ull,
+                          (static_cast<unsigned long long>(n) << 32) | (static_cast<unsigned long long>(orb + 1) << 4) |
+                              unsigned(code));
+        }
+    }
+}
+
+hipError_t launch_health_norms(const DevInst *insts, const WorkItem *work, int n_items, const int *step_ctr,
+                               int stride, const HealthArgs &h, int fp64, hipStream_t s) {
+    if (n_items <= 0 || stride <= 0 || !h.health) return hipSuccess;
+    if (fp64)
+        hipLaunchKernelGGL(k_health_norms<double2>, dim3(n_items), dim3(256), 0, s, insts, work, step_ctr, stride, h);
+    else
+        hipLaunchKernelGGL(k_health_norms<float2>, dim3(n_items), dim3(256), 0, s, insts, work, step_ctr, stride, h);
     return hipGetLastError();
 }
 

@@ -1019,6 +1019,7 @@ void k_propagate(PropArgs a) {
                     const double keq = kcart[3 * k + q] + Am[3 + q];
                     wacc[4 * wave + q] += fo * (kin + keq * nrm);
                 }
+                wacc[4 * wave + 3] += fo * nrm;  // charge, for the numeric health check
             }
         }
     }
@@ -1035,12 +1036,11 @@ void k_propagate(PropArgs a) {
         nl_combine();
         __syncthreads();
     }
-    if (tid < 3) {
+    if (tid < 4) {  // current (x, y, z) and charge of this work item
         double s = 0.0;
         for (int w = 0; w < NW; ++w) s += wacc[4 * w + tid];
         auto *jp = gview_w(I.j_part + 4 * w_slot);
         jp[tid] = s;
-        if (tid == 0) jp[3] = 0.0;
     }
 #undef TDKS_ZOK
 }

@@ -59,6 +59,9 @@ struct TableSet {
     std::vector<double> atom_tau, atom_par;
     int nat = 0;
     int cls = -1;
+    // sum over atoms of |E_s| ||f_s||^2 + |E_p| sum_i ||f_p,i||^2 (with |d| <= Rc): a bound of
+    // the operator norm of V_NL (each channel is the rank-one E |P><P|)
+    double nl_bound = 0.0;
     // device copies
     int *d_col_atom = nullptr, *d_col_j01 = nullptr;
     uint32_t *d_pt_pack = nullptr;
@@ -81,10 +84,13 @@ struct InstHost {
     double lat[3][3], B[3][3], c[3][3], g[3][3], hv[3][3];
     double omega, dV;
     std::vector<double> kcart, kw, occ, vloc, vhxc_frozen;
+    // |lambda| bound of h_kappa for the health check: lam0 + |A| lamA + |A|^2 / 2
+    double lam0 = 0.0, lamA = 0.0;
     int table = -1;
     int cls = -1;
     int wbeg = 0, wend = 0;  // work items (global indices) of this instance
     int nslot = 0;
+    size_t norm0_off = 0;    // first of this instance's reference norms in d_norm0
     void *d_u = nullptr;
     double *d_kcart = nullptr, *d_kw = nullptr, *d_occ = nullptr;
     double *d_rho_part = nullptr, *d_j_part = nullptr;
@@ -131,7 +137,17 @@ struct tdks_ctx {
     double *d_A = nullptr;
     size_t A_cap = 0;
     double *h_A = nullptr;  // pinned staging
-    int *d_ctrs = nullptr;  // [0] A row, [1] record index, [2] always 0
+    int *d_ctrs = nullptr;  // [0] A row, [1] steps since the load, [2] always 0
+    int rstride = 1;        // a current is recorded every rstride-th step
+    // numeric health check (per instance): charge at load, accumulated log of the per-step norm
+    // bound, first violation; per-step log bound per A row (host staging + device copy); norms
+    // of every orbital at load when the per-orbital check is on
+    double *d_q0 = nullptr, *d_lcum = nullptr;
+    unsigned long long *d_health = nullptr, *h_health = nullptr;
+    hipEvent_t ev_health = nullptr;
+    bool health_pending = false;
+    double *d_logF = nullptr, *h_logF = nullptr;
+    double *d_norm0 = nullptr;
     double *d_jpre = nullptr, *d_jobs = nullptr, *d_Aobs = nullptr;
     std::vector<double> jpre;
     // ground-state preparation (allocated on first use): input density of the mixing,
@@ -166,6 +182,19 @@ struct tdks_ctx {
             opt.free(p, opt.alloc_user);
         else
             (void)hipFree(p);
+    }
+    HealthArgs health(bool check) const {
+        HealthArgs h;
+        h.q0 = d_q0;
+        h.lcum = d_lcum;
+        h.logF = d_logF;
+        h.arow = d_ctrs;
+        h.health = check ? d_health : nullptr;
+        h.set_ref = 0;
+        h.rstride = rstride;
+        h.row_ctr = nullptr;
+        h.tol = fp64 ? 1e-9 : 1e-4;
+        return h;
     }
     void drop_graphs() {
         if (g_chunk) (void)hipGraphExecDestroy(g_chunk);
@@ -287,6 +316,7 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         const tdks_species &sp = d.species[d.atom_species[a]];
         if (!(sp.Rc > 0.0) || !(sp.rc > 0.0)) return fail(TDKS_E_ARG, "species radii must be positive");
         const double gcut = std::exp(-sp.Rc * sp.Rc / (2.0 * sp.rc * sp.rc));
+        double sg2 = 0.0;  // sum of g^2 over the support
         std::vector<int> hits(I.ng, 0);
         std::map<int, std::vector<std::pair<int, std::pair<int, double>>>> bycol;  // j01 -> (j2u, (p, g))
         for (int n0 = -2; n0 <= 2; ++n0)
@@ -308,10 +338,15 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
                         if (u0 < 0 || u0 >= 3 * I.N[0] || u1 < 0 || u1 >= 3 * I.N[1] || u2 < 0 || u2 >= 3 * I.N[2])
                             return fail(TDKS_E_ARG, "atom %d: projector support outside the neighbouring cells", a);
                         const double g = std::max(0.0, std::exp(-d2 / (2.0 * sp.rc * sp.rc)) - gcut);
+                        sg2 += g * g;
                         bycol[u0 | (u1 << 8)].push_back({u2, {p, g}});
                     }
                 }
         if (bycol.empty()) return fail(TDKS_E_ARG, "atom %d has no projector support points", a);
+        {
+            const double ns = T.atom_par[4 * a + 2], np = T.atom_par[4 * a + 3];
+            T.nl_bound += (std::fabs(sp.Es) * ns * ns + std::fabs(sp.Ep) * np * np * sp.Rc * sp.Rc) * sg2 * I.dV;
+        }
         // reference step r of each column image: the a_3 offset that brings its points
         // closest to the atom (d_ref = dcol + r a_3/N3); entries store j2 - r, so that
         // every offset the kernels form from tables stays small
@@ -555,10 +590,27 @@ int for_classes(tdks_ctx *c, F &&launch) {
     return TDKS_OK;
 }
 
+// Where a step reads its A table and puts its per-work-item partial sums and its recorded
+// currents: the context's own buffers (tdks_step), or the caller's A table and current buffer
+// with the partials in the static scratch array (tdks_step_noalloc).
+struct StepTarget {
+    const DevInst *insts;  // instance table whose rho_part / j_part receive the partials
+    const double *A;       // A table [rows][2][3]
+    const double *logF;    // per-row log norm bound, or null
+    double *trace;         // recorded currents [n_inst][jstride][3]
+    int jstride;
+    const int *row_ctr;    // record row (every step), or null: steps since the load / rstride
+};
+
+StepTarget own_target(const tdks_ctx *c) {
+    return StepTarget{c->d_insts, c->d_A, c->d_logF, c->d_trace, int(c->trace_cap), nullptr};
+}
+
 // the propagation launches of one step of every instance (mode STEP or PREDICT)
-int enqueue_propagation(tdks_ctx *c, int mode) {
+int enqueue_propagation(tdks_ctx *c, int mode, const StepTarget &t) {
     return for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
-        PropArgs a = class_args(c, S, mode, c->d_A, c->d_ctrs);
+        PropArgs a = class_args(c, S, mode, t.A, c->d_ctrs);
+        a.insts = t.insts;
         a.work = c->d_work + S.wbeg;
         HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
         return TDKS_OK;
@@ -571,8 +623,10 @@ bool predictor_corrector(const tdks_ctx *c) {
 
 // after the predictor: its density, v~ = v_Hxc[rho~] (kept apart), and the mid-step potential
 // v_loc + (v_Hxc[rho(t_n)] + v~) / 2 for the corrector; the predictor's current is discarded
-int enqueue_predictor_tail(tdks_ctx *c) {
-    HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_jobs, 1, nullptr, c->stream));
+int enqueue_predictor_tail(tdks_ctx *c, const StepTarget &t) {
+    HealthArgs none = c->health(false);
+    none.q0 = nullptr;
+    HIPCHK(launch_reduce(t.insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_jobs, 1, nullptr, none, c->stream));
     HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc_pred, c->d_vtot,
                       c->fp64, c->stream));
     HIPCHK(launch_vmid(c->d_insts, c->n_inst, c->ng_max, c->d_vloc, c->d_vhxc, c->d_vhxc_pred, c->d_vtot, c->fp64,
@@ -580,10 +634,17 @@ int enqueue_predictor_tail(tdks_ctx *c) {
     return TDKS_OK;
 }
 
-// after the step: density and recorded current, v_Hxc[rho(t_{n+1})], counters
-int enqueue_step_tail(tdks_ctx *c) {
-    HIPCHK(launch_reduce(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_trace, int(c->trace_cap),
-                         c->d_ctrs + 1, c->stream));
+// after the step: the per-orbital norm check when due, density, recorded current and the
+// charge check, v_Hxc[rho(t_{n+1})], counters
+int enqueue_step_tail(tdks_ctx *c, const StepTarget &t) {
+    HealthArgs h = c->health(true);
+    h.logF = t.logF;
+    h.row_ctr = t.row_ctr;
+    if (c->opt.norm_stride > 0)
+        HIPCHK(launch_health_norms(c->d_insts, c->d_work, int(c->work.size()), c->d_ctrs + 1, c->opt.norm_stride, h,
+                                   c->fp64, c->stream));
+    HIPCHK(launch_reduce(t.insts, 0, c->n_inst, c->ng_max, c->d_rho, t.trace, t.jstride, c->d_ctrs + 1, h,
+                         c->stream));
     if (c->opt.hxc_mode == TDKS_HXC_SCF)
         HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot,
                           c->fp64, c->stream));
@@ -591,15 +652,16 @@ int enqueue_step_tail(tdks_ctx *c) {
     return TDKS_OK;
 }
 
-// enqueue one time step of every instance (graph-capturable)
-int enqueue_step(tdks_ctx *c) {
+// enqueue one time step of every instance (graph-capturable; allocates nothing)
+int enqueue_step(tdks_ctx *c, const StepTarget &t) {
     if (predictor_corrector(c)) {
-        CHK(enqueue_propagation(c, MODE_PREDICT));
-        CHK(enqueue_predictor_tail(c));
+        CHK(enqueue_propagation(c, MODE_PREDICT, t));
+        CHK(enqueue_predictor_tail(c, t));
     }
-    CHK(enqueue_propagation(c, MODE_STEP));
-    return enqueue_step_tail(c);
+    CHK(enqueue_propagation(c, MODE_STEP, t));
+    return enqueue_step_tail(c, t);
 }
+int enqueue_step(tdks_ctx *c) { return enqueue_step(c, own_target(c)); }
 
 int build_graph(tdks_ctx *c, int nsteps, hipGraphExec_t *out) {
     hipGraph_t g = nullptr;
@@ -618,15 +680,16 @@ int build_graph(tdks_ctx *c, int nsteps, hipGraphExec_t *out) {
     return TDKS_OK;
 }
 
+// room for `need` recorded currents per instance
 int ensure_trace(tdks_ctx *c, size_t need) {
     if (need <= c->trace_cap) return TDKS_OK;
     size_t cap = std::max<size_t>(need, std::max<size_t>(2 * c->trace_cap, 1024));
     double *nt = static_cast<double *>(c->alloc(sizeof(double) * 3 * cap * c->n_inst));
     if (!nt) return fail(TDKS_E_OOM, "trace allocation failed");
-    if (c->d_trace && c->steps_done > 0) {
+    const size_t rec = size_t(c->steps_done / c->rstride);
+    if (c->d_trace && rec > 0) {
         HIPCHK(hipMemcpy2DAsync(nt, sizeof(double) * 3 * cap, c->d_trace, sizeof(double) * 3 * c->trace_cap,
-                                sizeof(double) * 3 * c->steps_done, c->n_inst, hipMemcpyDeviceToDevice,
-                                c->stream));
+                                sizeof(double) * 3 * rec, c->n_inst, hipMemcpyDeviceToDevice, c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->release(c->d_trace);
@@ -641,18 +704,21 @@ int ensure_A(tdks_ctx *c, size_t n) {
     HIPCHK(hipStreamSynchronize(c->stream));
     size_t cap = std::max<size_t>(n, std::max<size_t>(2 * c->A_cap, 1024));
     // both new buffers first: on failure the old pair stays in place, consistent with A_cap
+    // rows of 6 A components, then one log norm bound per row (d_logF follows d_A)
     double *hn = nullptr;
-    if (hipHostMalloc(reinterpret_cast<void **>(&hn), sizeof(double) * 6 * cap, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(reinterpret_cast<void **>(&hn), sizeof(double) * 7 * cap, hipHostMallocDefault) != hipSuccess)
         return fail(TDKS_E_OOM, "pinned A table allocation failed");
-    double *na = static_cast<double *>(c->alloc(sizeof(double) * 6 * cap));
+    double *na = static_cast<double *>(c->alloc(sizeof(double) * 7 * cap));
     if (!na) {
         (void)hipHostFree(hn);
         return fail(TDKS_E_OOM, "A table allocation failed");
     }
     c->release(c->d_A);
     c->d_A = na;
+    c->d_logF = na + 6 * cap;
     if (c->h_A) (void)hipHostFree(c->h_A);
     c->h_A = hn;
+    c->h_logF = hn + 6 * cap;
     c->A_cap = cap;
     c->drop_graphs();
     return TDKS_OK;
@@ -669,8 +735,10 @@ size_t orb_bytes(const tdks_ctx *c, const InstHost &I) {
 }
 
 // observe: current (and density) of instance range for given A; writes d_jobs or d_jpre.
-// enqueue_observe leaves the work on the stream; d_Aobs must already hold A.
-int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int mode = MODE_OBSERVE) {
+// enqueue_observe leaves the work on the stream; d_Aobs must already hold A.  With set_ref the
+// charge becomes the instances' reference of the health check.
+int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int set_ref = 0) {
+    const int mode = MODE_OBSERVE;
     CHK(for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
         int wb = S.wend, we = S.wbeg;
         for (int i = i_first; i <= i_last; ++i) {
@@ -685,15 +753,17 @@ int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int mode
         HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
         return TDKS_OK;
     }));
-    HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr,
+    HealthArgs h = c->health(false);
+    h.set_ref = set_ref;
+    HIPCHK(launch_reduce(c->d_insts, i_first, i_last - i_first + 1, c->ng_max, c->d_rho, jdst, 1, nullptr, h,
                          c->stream));
     return TDKS_OK;
 }
 
-int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jdst) {
+int observe(tdks_ctx *c, int i_first, int i_last, const double A[3], double *jdst, int set_ref = 0) {
     double h[6] = {A[0], A[1], A[2], A[0], A[1], A[2]};
     HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
-    CHK(enqueue_observe(c, i_first, i_last, jdst));
+    CHK(enqueue_observe(c, i_first, i_last, jdst, set_ref));
     HIPCHK(hipStreamSynchronize(c->stream));
     return TDKS_OK;
 }
@@ -720,6 +790,77 @@ double kinetic_bound(const InstHost &I) {
     return b + kmax;
 }
 
+// log of the closed-form norm bound of one Taylor-4 step with A(t_n + dt/2) = Amid, for the
+// health check: F = min over |x| <= x_max of |T4(-i x)|^2 = 1 - x^6/72 + x^8/576, which is
+// f(x_max) while x_max < sqrt 6 and 0.25 beyond; x_max = |dt| max over instances of
+// lam0 + |A| lamA + |A|^2 / 2 (a bound of |lambda| of h_kappa, kappa = k + A).
+double step_log_bound(const tdks_ctx *c, const double *Amid) {
+    const double a = std::sqrt(Amid[0] * Amid[0] + Amid[1] * Amid[1] + Amid[2] * Amid[2]);
+    double lam = 0.0;
+    for (const InstHost &I : c->inst) lam = std::max(lam, I.lam0 + a * I.lamA + 0.5 * a * a);
+    const double x = std::fabs(c->opt.dt) * lam;
+    if (!(x < std::sqrt(6.0))) return std::log(0.25);
+    const double x2 = x * x, x6 = x2 * x2 * x2;
+    return std::log(1.0 - x6 / 72.0 + x6 * x2 / 576.0);
+}
+
+// copies an A table (HOST [n][2][3]) and its per-step norm bounds to the device (the A-table
+// row counter restarts at 0)
+int upload_A(tdks_ctx *c, int n_steps, const double *A_tab) {
+    CHK(ensure_A(c, size_t(n_steps)));
+    HIPCHK(hipEventSynchronize(c->ev_acopy));  // previous copy out of the staging buffer is done
+    std::memcpy(c->h_A, A_tab, sizeof(double) * 6 * n_steps);
+    for (int n = 0; n < n_steps; ++n) c->h_logF[n] = step_log_bound(c, A_tab + 6 * n);
+    HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_logF, c->h_logF, sizeof(double) * n_steps, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    return TDKS_OK;
+}
+
+// clears the health record of instances [i0, i1] and, with the per-orbital check on, takes
+// their present norms as the reference (the charge reference is set by the observation)
+int health_reset(tdks_ctx *c, int i0, int i1) {
+    if (c->health_pending) {  // a copy still in flight would bring the old record back
+        HIPCHK(hipEventSynchronize(c->ev_health));
+        c->health_pending = false;
+    }
+    std::fill(c->h_health + i0, c->h_health + i1 + 1, 0ull);
+    HIPCHK(launch_fill_int(reinterpret_cast<int *>(c->d_health + i0), 0, 2 * (i1 - i0 + 1), c->stream));
+    if (c->opt.norm_stride > 0)
+        for (int i = i0; i <= i1; ++i) {
+            const InstHost &I = c->inst[i];
+            HIPCHK(launch_norms(I.d_u, I.nk * I.nb, I.ng, I.dV, c->fp64, c->d_norm0 + I.norm0_off, c->stream));
+        }
+    return TDKS_OK;
+}
+
+// E_NUMERIC naming the first instance with a recorded violation, else OK
+int health_report(const tdks_ctx *c, const unsigned long long *h) {
+    static const char *what[] = {"", "non-finite current or charge", "charge above its value at the load",
+                                 "charge below the Taylor-4 norm bound", "orbital norm above its value at the load",
+                                 "orbital norm below the Taylor-4 norm bound"};
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (!h[i]) continue;
+        const int code = int(h[i] & 15u), step = int(h[i] >> 32);
+        const long long orb = static_cast<long long>((h[i] >> 4) & 0xfffffffull) - 1;
+        const InstHost &I = c->inst[i];
+        if (orb >= 0)
+            return fail(TDKS_E_NUMERIC, "instance %d, step %d after the load: %s (k %lld, band %lld)", i, step,
+                        what[code < 6 ? code : 0], orb / I.nb, orb % I.nb);
+        return fail(TDKS_E_NUMERIC, "instance %d, step %d after the load: %s", i, step, what[code < 6 ? code : 0]);
+    }
+    return TDKS_OK;
+}
+
+// the health record as of the last synchronisation point: waits for the stream
+int health_sync(tdks_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->h_health, c->d_health, sizeof(unsigned long long) * c->n_inst, hipMemcpyDeviceToHost));
+    c->health_pending = false;
+    return health_report(c, c->h_health);
+}
+
 }  // namespace
 
 extern "C" {
@@ -743,6 +884,8 @@ void tdks_destroy(tdks_ctx *c) {
     std::vector<void *> all = c->allocs;
     for (void *p : all) c->release(p);
     if (c->h_A) (void)hipHostFree(c->h_A);
+    if (c->h_health) (void)hipHostFree(c->h_health);
+    if (c->ev_health) (void)hipEventDestroy(c->ev_health);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->ev_acopy) (void)hipEventDestroy(c->ev_acopy);
@@ -766,6 +909,9 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         return fail(TDKS_E_ARG, "unknown hxc_mode %d", opt->hxc_mode);
     if (opt->propagator != TDKS_PROP_TAYLOR && opt->propagator != TDKS_PROP_PC)
         return fail(TDKS_E_ARG, "unknown propagator %d", opt->propagator);
+    if (opt->norm_stride < 0) return fail(TDKS_E_ARG, "norm_stride must be >= 0");
+    if (opt->record_stride < 0) return fail(TDKS_E_ARG, "record_stride must be >= 0");
+    c->rstride = opt->record_stride > 0 ? opt->record_stride : 1;
     c->fp64 = opt->precision == TDKS_FP64;
     c->n_inst = n_inst;
     c->chunk = opt->graph_steps == 0 ? 16 : opt->graph_steps;
@@ -819,6 +965,20 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
                 }
         }
         c->ng_max = std::max(c->ng_max, I.ng);
+    }
+    // |lambda| bound of each instance's h_kappa for the health check: kinetic bound at A = 0,
+    // |v_loc| and the V_NL bound, plus an allowance of 5 Ha for |v_Hxc|; with a field,
+    // |k + A|^2 / 2 + sum_d |(k + A).c_d| s1 grows by at most |A| (|k|max + s1 sum_d |c_d|) + |A|^2 / 2
+    for (InstHost &I : c->inst) {
+        double vmax = 0.0, kmax = 0.0, cs = 0.0;
+        for (double v : I.vloc) vmax = std::max(vmax, std::fabs(v));
+        for (int k = 0; k < I.nk; ++k) {
+            const double *kc = &I.kcart[3 * k];
+            kmax = std::max(kmax, std::sqrt(kc[0] * kc[0] + kc[1] * kc[1] + kc[2] * kc[2]));
+        }
+        for (int d = 0; d < 3; ++d) cs += 1.3722 * std::sqrt(I.g[d][d]);
+        I.lam0 = kinetic_bound(I) + vmax + c->tables[I.table].nl_bound + 5.0;
+        I.lamA = kmax + cs;
     }
     // shape classes and tiling
     for (int i = 0; i < n_inst; ++i) {
@@ -972,8 +1132,29 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     c->d_jpre = static_cast<double *>(c->alloc(sizeof(double) * 3 * n_inst));
     c->d_jobs = static_cast<double *>(c->alloc(sizeof(double) * 3 * n_inst));
     c->d_Aobs = static_cast<double *>(c->alloc(sizeof(double) * 6));
-    if (!c->d_rho || !c->d_vtot || !c->d_ctrs || !c->d_jpre || !c->d_jobs || !c->d_Aobs)
+    c->d_q0 = static_cast<double *>(c->alloc(sizeof(double) * n_inst));
+    c->d_lcum = static_cast<double *>(c->alloc(sizeof(double) * n_inst));
+    c->d_health = static_cast<unsigned long long *>(c->alloc(sizeof(unsigned long long) * n_inst));
+    if (!c->d_rho || !c->d_vtot || !c->d_ctrs || !c->d_jpre || !c->d_jobs || !c->d_Aobs || !c->d_q0 ||
+        !c->d_lcum || !c->d_health)
         return fail(TDKS_E_OOM, "device allocation failed");
+    if (hipHostMalloc(reinterpret_cast<void **>(&c->h_health), sizeof(unsigned long long) * n_inst,
+                      hipHostMallocDefault) != hipSuccess)
+        return fail(TDKS_E_OOM, "pinned health record allocation failed");
+    std::fill(c->h_health, c->h_health + n_inst, 0ull);
+    HIPCHK(hipEventCreateWithFlags(&c->ev_health, hipEventDisableTiming));
+    HIPCHK(hipMemset(c->d_health, 0, sizeof(unsigned long long) * n_inst));
+    HIPCHK(hipMemset(c->d_q0, 0, sizeof(double) * n_inst));
+    HIPCHK(hipMemset(c->d_lcum, 0, sizeof(double) * n_inst));
+    if (opt->norm_stride > 0) {
+        size_t norb = 0;
+        for (InstHost &I : c->inst) {
+            I.norm0_off = norb;
+            norb += size_t(I.nk) * I.nb;
+        }
+        c->d_norm0 = static_cast<double *>(c->alloc(sizeof(double) * norb));
+        if (!c->d_norm0) return fail(TDKS_E_OOM, "reference norm allocation failed");
+    }
     HIPCHK(hipMemset(c->d_ctrs, 0, sizeof(int) * 4));
     HIPCHK(hipMemset(c->d_rho, 0, sizeof(double) * ngm));
     std::vector<DevInst> dinst(n_inst);
@@ -1030,6 +1211,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.rho_part = I.d_rho_part;
         D.j_part = I.d_j_part;
         D.nslot = I.nslot;
+        D.norm0 = c->d_norm0 ? c->d_norm0 + I.norm0_off : nullptr;
     }
     {
         std::vector<DevInst> tmp = dinst;
@@ -1089,9 +1271,11 @@ int tdks_load_orbitals(tdks_ctx *c, int i, const void *u, int where) {
             c->release(stage);
         }
     }
-    // density, v_Hxc and the current before the field (A = 0)
+    // density, v_Hxc and the current before the field (A = 0); the charge and the norms of the
+    // new orbitals become the health check's references
     const double zero[3] = {0.0, 0.0, 0.0};
-    CHK(observe(c, i, i, zero, c->d_jpre));
+    CHK(health_reset(c, i, i));
+    CHK(observe(c, i, i, zero, c->d_jpre, 1));
     if (c->opt.hxc_mode == TDKS_HXC_SCF) {
         HIPCHK(launch_hxc(c->d_insts, i, 1, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64, c->stream));
     }
@@ -1112,15 +1296,13 @@ int tdks_step(tdks_ctx *c, int n_steps, const double *A_tab) {
     if (!A_tab) return fail(TDKS_E_ARG, "null A table");
     for (int i = 0; i < c->n_inst; ++i)
         if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+    // the health record copied after an earlier call, if it has arrived (no wait)
+    if (c->health_pending && hipEventQuery(c->ev_health) == hipSuccess) c->health_pending = false;
+    if (!c->health_pending) CHK(health_report(c, c->h_health));
     CHK(sync_in(c));
-    CHK(ensure_trace(c, size_t(c->steps_done) + n_steps));
-    CHK(ensure_A(c, size_t(n_steps)));
-    HIPCHK(hipEventSynchronize(c->ev_acopy));  // previous copy out of the staging buffer is done
-    std::memcpy(c->h_A, A_tab, sizeof(double) * 6 * n_steps);
-    HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
-    // A row counter restarts for this call; the record counter continues
-    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    CHK(ensure_trace(c, size_t(c->steps_done + n_steps) / c->rstride));
+    // A row counter restarts for this call; the step counter continues
+    CHK(upload_A(c, n_steps, A_tab));
     int done = 0;
     if (c->chunk > 0) {
         if (!c->g_one) CHK(build_graph(c, 1, &c->g_one));
@@ -1137,8 +1319,19 @@ int tdks_step(tdks_ctx *c, int n_steps, const double *A_tab) {
         for (; done < n_steps; ++done) CHK(enqueue_step(c));
     }
     c->steps_done += n_steps;
+    HIPCHK(hipMemcpyAsync(c->h_health, c->d_health, sizeof(unsigned long long) * c->n_inst, hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipEventRecord(c->ev_health, c->stream));
+    c->health_pending = true;
     CHK(sync_out(c));
     return TDKS_OK;
+}
+
+int tdks_check(tdks_ctx *c, unsigned long long *info) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    const int rc = health_sync(c);
+    if (info) std::copy(c->h_health, c->h_health + c->n_inst, info);
+    return rc;
 }
 
 int tdks_steps_done(tdks_ctx *c) { return c ? c->steps_done : 0; }
@@ -1224,7 +1417,9 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
                               c->fp64, c->stream));
     }
     // the prepared state: density, v_Hxc and the current before the field of the final orbitals
-    CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jpre));
+    // (and the health check's references)
+    CHK(health_reset(c, 0, c->n_inst - 1));
+    CHK(enqueue_observe(c, 0, c->n_inst - 1, c->d_jpre, 1));
     if (scf)
         HIPCHK(launch_hxc(c->d_insts, 0, c->n_inst, c->ng_max, c->d_rho, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64,
                           c->stream));
@@ -1246,13 +1441,13 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
 
 int tdks_current(tdks_ctx *c, int mode, double *out, size_t cap, size_t *n_written) {
     if (!c || !out) return fail(TDKS_E_ARG, "null argument");
-    const size_t ns = size_t(c->steps_done);
+    const size_t ns = size_t(c->steps_done / c->rstride);  // recorded currents
     const size_t rows = (mode == TDKS_PER_GROUP) ? c->groups.size() : size_t(c->n_inst);
     if (mode != TDKS_PER_GROUP && mode != TDKS_PER_INSTANCE) return fail(TDKS_E_ARG, "bad mode");
     if (cap < rows * ns * 3) return fail(TDKS_E_ARG, "capacity %zu < %zu", cap, rows * ns * 3);
-    // trace row r of instance i holds J^{r+1}
+    // trace row r of instance i holds J^{(r+1) rstride}
     std::vector<double> tr(size_t(c->n_inst) * 3 * std::max<size_t>(ns, 1));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(health_sync(c));
     if (ns > 0)
         HIPCHK(hipMemcpy2D(tr.data(), sizeof(double) * 3 * ns, c->d_trace, sizeof(double) * 3 * c->trace_cap,
                            sizeof(double) * 3 * ns, c->n_inst, hipMemcpyDeviceToHost));
@@ -1260,7 +1455,8 @@ int tdks_current(tdks_ctx *c, int mode, double *out, size_t cap, size_t *n_writt
         for (size_t n = 0; n < ns; ++n)
             for (int q = 0; q < 3; ++q)
                 if (!std::isfinite(tr[(size_t(i) * ns + n) * 3 + q]))
-                    return fail(TDKS_E_NUMERIC, "non-finite current in instance %d at step %zu", i, n + 1);
+                    return fail(TDKS_E_NUMERIC, "non-finite current in instance %d at step %zu", i,
+                                (n + 1) * c->rstride);
     if (mode == TDKS_PER_INSTANCE) {
         for (int i = 0; i < c->n_inst; ++i)
             for (size_t n = 0; n < ns; ++n)
@@ -1403,13 +1599,8 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
     for (int i = 0; i < c->n_inst; ++i)
         if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
     CHK(sync_in(c));
-    CHK(ensure_trace(c, size_t(c->steps_done) + n_steps));
-    CHK(ensure_A(c, size_t(n_steps)));
-    HIPCHK(hipEventSynchronize(c->ev_acopy));
-    std::memcpy(c->h_A, A_tab, sizeof(double) * 6 * n_steps);
-    HIPCHK(hipMemcpyAsync(c->d_A, c->h_A, sizeof(double) * 6 * n_steps, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipEventRecord(c->ev_acopy, c->stream));
-    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    CHK(ensure_trace(c, size_t(c->steps_done + n_steps) / c->rstride));
+    CHK(upload_A(c, n_steps, A_tab));
     // per step: [0] start, [1] after the predictor's propagation, [2] after its tail (PC only),
     // [3] after the step's propagation, [4] end
     std::vector<hipEvent_t> ev(5 * n_steps);
@@ -1418,13 +1609,14 @@ int tdks_time_kernels(tdks_ctx *c, int n_steps, const double *A_tab, double *out
     int rc = TDKS_OK;
     for (int s = 0; s < n_steps && rc == TDKS_OK; ++s) {
         HIPCHK(hipEventRecord(ev[5 * s], c->stream));
-        if (pc) CHK(enqueue_propagation(c, MODE_PREDICT));
+        const StepTarget t = own_target(c);
+        if (pc) CHK(enqueue_propagation(c, MODE_PREDICT, t));
         HIPCHK(hipEventRecord(ev[5 * s + 1], c->stream));
-        if (pc) CHK(enqueue_predictor_tail(c));
+        if (pc) CHK(enqueue_predictor_tail(c, t));
         HIPCHK(hipEventRecord(ev[5 * s + 2], c->stream));
-        CHK(enqueue_propagation(c, MODE_STEP));
+        CHK(enqueue_propagation(c, MODE_STEP, t));
         HIPCHK(hipEventRecord(ev[5 * s + 3], c->stream));
-        CHK(enqueue_step_tail(c));
+        CHK(enqueue_step_tail(c, t));
         HIPCHK(hipEventRecord(ev[5 * s + 4], c->stream));
     }
     HIPCHK(hipStreamSynchronize(c->stream));

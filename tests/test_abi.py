@@ -48,6 +48,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(tdks_options, stream), offsetof(tdks_options, alloc_user),
          offsetof(tdks_options, block_size), offsetof(tdks_options, graph_steps),
          offsetof(tdks_options, waves_per_simd));
+  printf("%zu %zu %zu\\n", offsetof(tdks_options, propagator), offsetof(tdks_options, norm_stride),
+         offsetof(tdks_options, record_stride));
   return 0;
 }
 """)
@@ -59,6 +61,7 @@ int main(void) {
     assert vals[3:7] == [D.n_k.offset, D.group.offset, D.v_hxc_frozen.offset, D.species.offset]
     assert vals[7:12] == [O.stream.offset, O.alloc_user.offset, O.block_size.offset, O.graph_steps.offset,
                           O.waves_per_simd.offset]
+    assert vals[12:15] == [O.propagator.offset, O.norm_stride.offset, O.record_stride.offset]
 
 
 def test_default_options():
@@ -67,6 +70,7 @@ def test_default_options():
     lib.tdks_default_options(ctypes.byref(opt))
     assert opt.precision == _lib.FP64 and opt.taylor_order == 4 and opt.dt == 0.02
     assert opt.hxc_mode == _lib.HXC_SCF and opt.graph_steps == 16
+    assert opt.norm_stride == 0 and opt.record_stride == 0
 
 
 def _desc(inst, k):
@@ -90,7 +94,7 @@ def _desc(inst, k):
 
 
 @pytest.mark.parametrize("case", ["rc_too_large", "bad_order", "no_bands", "grid_too_big", "bad_species",
-                                  "fp64_lds", "axis_too_small"])
+                                  "fp64_lds", "axis_too_small", "norm_stride", "record_stride"])
 def test_argument_errors_before_device_work(case):
     lib = _lib.load()
     sp = W.Species(D=-1.0, w=1.0, Rc=3.5)
@@ -115,11 +119,15 @@ def test_argument_errors_before_device_work(case):
     lib.tdks_default_options(ctypes.byref(opt))
     if case == "bad_order":
         opt.taylor_order = 2
+    if case == "norm_stride":
+        opt.norm_stride = -1
+    if case == "record_stride":
+        opt.record_stride = -3
     ctx = ctypes.c_void_p()
     rc = lib.tdks_create(ctypes.byref(d), 1, ctypes.byref(opt), ctypes.byref(ctx))
     want = {"rc_too_large": _lib.E_ARG, "bad_order": _lib.E_UNSUPPORTED, "no_bands": _lib.E_ARG,
             "grid_too_big": _lib.E_UNSUPPORTED, "bad_species": _lib.E_ARG, "fp64_lds": _lib.E_UNSUPPORTED,
-            "axis_too_small": _lib.E_UNSUPPORTED}[case]
+            "axis_too_small": _lib.E_UNSUPPORTED, "norm_stride": _lib.E_ARG, "record_stride": _lib.E_ARG}[case]
     assert rc == want, lib.tdks_last_error()
     assert ctx.value is None
     assert len(lib.tdks_last_error()) > 0
