@@ -204,6 +204,29 @@ int tdks_load_orbitals(tdks_ctx *ctx, int inst, const void *u, int where);
  * enqueued; the message names the instance, the step and the check). */
 int tdks_step(tdks_ctx *ctx, int n_steps, const double *A_tab);
 
+/* Allocation-free variant of tdks_step for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Advances every instance by n_steps steps exactly as tdks_step does, with the same
+ * kernels, but the A table comes from the caller's device memory (A_dev, DEVICE
+ * [n_steps][2][3], as A_tab), the currents go to the caller's device buffer (j_dev,
+ * DEVICE [n_inst][n_steps][3]: J^{n+1} of each step of the call, the current itself, not
+ * delta J; subtract tdks_current_pre; record_stride does not apply), and the per-work-item
+ * partial sums of the density and current live in one static device array of 32 MiB per
+ * GPU (held until the process ends) instead of the context's buffers.  The call allocates
+ * nothing (no hipMalloc, hipFree, pinned or host staging) and does not synchronise: it only
+ * enqueues kernels on the context's stream, fenced against the caller's stream as every call
+ * is, so a caller may capture it into a HIP graph.  Every step overwrites the partial sums
+ * it reads, so the array needs no clearing; all calls on one GPU share it, so calls that
+ * overlap on one GPU (contexts driven from different streams or threads) race and must be
+ * serialised by the caller.  The health check runs with the step-independent floor 0.25 of
+ * |T4(-i x)|^2 for its lower bound (the A table is not read on the host).  After such a
+ * call tdks_current returns E_STATE until the next load (these steps have no trace rows).
+ * Errors: E_ARG (null buffers, n_steps < 0, another device current), E_STATE (an instance
+ * not loaded), E_UNSUPPORTED (the context's partial sums, sum over instances of
+ * (8 N_g + 32) bytes per work item with 256-byte alignment, exceed 32 MiB; tdks_step has no
+ * such limit), E_HIP. */
+int tdks_step_noalloc(tdks_ctx *ctx, int n_steps, const double *A_dev, double *j_dev);
+
 /* Waits for the context's work and returns E_NUMERIC if any instance failed the health
  * check since its load (the message names the first such instance, the step counted from
  * the load, the check, and for an orbital check its k and band), else TDKS_OK.  info

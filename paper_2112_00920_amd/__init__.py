@@ -192,6 +192,19 @@ class Propagator:
         A = np.ascontiguousarray(A_tab, dtype=np.float64).reshape(-1, 2, 3)
         _lib.check(self._lib.tdks_step(self._ctx, len(A), _ptr(A)))
 
+    def step_noalloc(self, A_dev, j_dev):
+        """tdks_step_noalloc: A_dev and j_dev are float64 device tensors [n][2][3] and
+        [n_inst][n][3] (contiguous); j_dev receives J^{n+1} of every step of the call."""
+        t = self._torch
+        if t is None or not (isinstance(A_dev, t.Tensor) and isinstance(j_dev, t.Tensor)):
+            raise TypeError("step_noalloc takes torch device tensors")
+        n = A_dev.shape[0]
+        for x, shape in ((A_dev, (n, 2, 3)), (j_dev, (self.n_inst, n, 3))):
+            if not (x.is_cuda and x.dtype == t.float64 and x.is_contiguous() and tuple(x.shape) == shape):
+                raise ValueError(f"expected a contiguous float64 device tensor of shape {shape}")
+        _lib.check(self._lib.tdks_step_noalloc(self._ctx, int(n), ctypes.c_void_p(A_dev.data_ptr()),
+                                               ctypes.c_void_p(j_dev.data_ptr())))
+
     def ground_state(self, n_iter: int, tau: float, mix: float = 0.5) -> np.ndarray:
         """Imaginary-time ground-state preparation of every instance (tdks_ground_state);
         returns the last iteration's density residual per instance."""

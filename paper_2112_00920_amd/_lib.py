@@ -77,6 +77,7 @@ SYMBOLS = {
     "tdks_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p]),
     "tdks_steps_done": (ctypes.c_int, [ctypes.c_void_p]),
     "tdks_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "tdks_step_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "tdks_ground_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_void_p]),
     "tdks_current": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, c_double_p, ctypes.c_size_t,

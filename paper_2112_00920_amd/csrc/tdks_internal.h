@@ -74,7 +74,8 @@ struct DevInst {
 struct HealthArgs {
     double *q0;                     // [n_inst] charge at load (written when set_ref)
     double *lcum;                   // [n_inst] accumulated log F since load
-    const double *logF;             // [A rows] log F of each step, or null (no lower bound)
+    const double *logF;             // [A rows] log F of each step, or null: logF_floor every step
+    double logF_floor;              // log 0.25, the least |T4(-i x)|^2 over |x| <= 2 sqrt 2
     const int *arow;                // A-table row of the step
     unsigned long long *health;     // [n_inst] first violation, 0 if none (null: no check)
     const int *row_ctr;             // record row of every step instead (or null)

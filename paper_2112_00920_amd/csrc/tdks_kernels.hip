@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0,
             h.lcum[inst] = 0.0;
         }
         if (lane == 0 && step_ctr && h.health) {
-            const double lc = h.lcum[inst] + (h.logF ? h.logF[*h.arow] : 0.0);
+            const double lc = h.lcum[inst] + (h.logF ? h.logF[*h.arow] : h.logF_floor);
             h.lcum[inst] = lc;
             const double q0 = h.q0[inst];
             int code = 0;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_reduce(const DevInst *insts, int inst0,
                 code = 1;
             else if (q > q0 * (1.0 + h.tol))
                 code = 2;
-            else if (h.logF && q < q0 * (exp(lc) - h.tol))
+            else if (q < q0 * (exp(lc) - h.tol))
                 code = 3;
             if (code)
                 atomicCAS(h.health + inst, 0ull, (static_cast<unsigned long long>(n) << 32) | unsigned(code));
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(256) void k_health_norms(const DevInst *insts, cons
     const DevInst &I = insts[wi.inst];
     if (!I.norm0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double lc = h.lcum[wi.inst] + (h.logF ? h.logF[*h.arow] : 0.0);
+    const double lc = h.lcum[wi.inst] + (h.logF ? h.logF[*h.arow] : h.logF_floor);
     const int norb = wi.nk * wi.nb;
     for (int o = wave; o < norb; o += 4) {
         const int k = wi.k0 + o / wi.nb, b = wi.b0 + o % wi.nb;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_health_norms(const DevInst *insts, cons
                 code = 1;
             else if (sq > n0 * (1.0 + h.tol))
                 code = 4;
-            else if (h.logF && sq < n0 * (exp(lc) - h.tol))
+            else if (sq < n0 * (exp(lc) - h.tol))
                 code = 5;
             if (code)
                 atomicCAS(h.health + wi.inst, 0ull,

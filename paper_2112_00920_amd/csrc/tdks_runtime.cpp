@@ -17,10 +17,18 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace tdks;
+
+// Partial sums of the allocation-free step (tdks_step_noalloc): a static device array instead
+// of the context's buffers.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code the name is only a stand-in: the device address comes from
+// hipGetSymbolAddress (scratch_address below), once per device.
+constexpr size_t kScratchBytes = size_t(32) << 20;  // 32 MiB
+static __device__ __align__(256) char scratch[kScratchBytes];
 
 namespace {
 
@@ -36,6 +44,15 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+// device address of the static scratch array on device dev (the current device), resolved
+// with hipGetSymbolAddress the first time a context is created on that device
+int scratch_address(int dev, void **out);
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+bool g_scratch_set[kMaxDevices];
+
 #define HIPCHK(expr)                                                                      \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
@@ -43,6 +60,22 @@ int fail(int code, const char *fmt, ...) {
             return fail(TDKS_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
                         __FILE__, __LINE__);                                              \
     } while (0)
+
+int scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TDKS_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_set[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TDKS_E_HIP, "hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+        g_scratch_set[dev] = true;
+    }
+    *out = g_scratch_ptr[dev];
+    return TDKS_OK;
+}
 
 struct TableSet {
     std::vector<int> col_atom, col_j01;
@@ -110,6 +143,13 @@ struct ShapeClass {
 struct tdks_ctx {
     tdks_options opt;
     int fp64 = 1;
+    int device = 0;
+    // allocation-free step: the device address of the static scratch array, the bytes this
+    // context's partial sums need there, and the instance table pointing into it
+    void *scratch = nullptr;
+    size_t scratch_need = 0;
+    DevInst *d_insts_scr = nullptr;
+    bool noalloc_steps = false;  // steps since the load whose currents went to a caller's buffer
     int n_inst = 0;
     std::vector<InstHost> inst;
     std::vector<TableSet> tables;
@@ -193,6 +233,7 @@ struct tdks_ctx {
         h.set_ref = 0;
         h.rstride = rstride;
         h.row_ctr = nullptr;
+        h.logF_floor = std::log(0.25);
         h.tol = fp64 ? 1e-9 : 1e-4;
         return h;
     }
@@ -1081,7 +1122,9 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         if (std::find(c->groups.begin(), c->groups.end(), I.group) == c->groups.end()) c->groups.push_back(I.group);
     }
     std::sort(c->groups.begin(), c->groups.end());
-    // device side: stream, events, memory
+    // device side: stream, events, memory; the scratch array's address on this device
+    HIPCHK(hipGetDevice(&c->device));
+    CHK(scratch_address(c->device, &c->scratch));
     HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -1217,6 +1260,22 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         std::vector<DevInst> tmp = dinst;
         CHK(upload(c, &c->d_insts, tmp));
     }
+    // the same table with the partial sums in the static scratch array (allocation-free step),
+    // when they fit: per instance [nslot][ng] densities, then [nslot][4] currents, 256-aligned
+    {
+        std::vector<DevInst> scr = dinst;
+        size_t off = 0;
+        auto al256 = [](size_t x) { return (x + 255) & ~size_t(255); };
+        for (int i = 0; i < n_inst; ++i) {
+            const InstHost &I = c->inst[i];
+            scr[i].rho_part = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + off);
+            off = al256(off + sizeof(double) * size_t(I.nslot) * I.ng);
+            scr[i].j_part = reinterpret_cast<double *>(static_cast<char *>(c->scratch) + off);
+            off = al256(off + sizeof(double) * 4 * size_t(I.nslot));
+        }
+        c->scratch_need = off;
+        if (off <= kScratchBytes) CHK(upload(c, &c->d_insts_scr, scr));
+    }
     CHK(upload(c, &c->d_work, c->work));
     HIPCHK(launch_vtot(c->d_insts, 0, n_inst, c->ng_max, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64, c->stream));
     c->jpre.assign(3 * n_inst, 0.0);
@@ -1285,6 +1344,7 @@ int tdks_load_orbitals(tdks_ctx *c, int i, const void *u, int where) {
     HIPCHK(hipStreamSynchronize(c->stream));
     I.loaded = true;
     c->steps_done = 0;
+    c->noalloc_steps = false;
     CHK(sync_out(c));
     return TDKS_OK;
 }
@@ -1323,6 +1383,31 @@ int tdks_step(tdks_ctx *c, int n_steps, const double *A_tab) {
                           c->stream));
     HIPCHK(hipEventRecord(c->ev_health, c->stream));
     c->health_pending = true;
+    CHK(sync_out(c));
+    return TDKS_OK;
+}
+
+int tdks_step_noalloc(tdks_ctx *c, int n_steps, const double *A_dev, double *j_dev) {
+    if (!c) return fail(TDKS_E_ARG, "null context");
+    if (n_steps < 0) return fail(TDKS_E_ARG, "n_steps < 0");
+    if (c->scratch_need > kScratchBytes)
+        return fail(TDKS_E_UNSUPPORTED, "the partial sums of this context need %zu bytes; the static scratch array "
+                    "holds %zu (use tdks_step)", c->scratch_need, kScratchBytes);
+    if (n_steps == 0) return TDKS_OK;
+    if (!A_dev || !j_dev) return fail(TDKS_E_ARG, "null A table or current buffer");
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!c->inst[i].loaded) return fail(TDKS_E_STATE, "instance %d has no orbitals loaded", i);
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(TDKS_E_ARG, "the context lives on device %d but device %d is current", c->device, dev);
+    CHK(sync_in(c));
+    // the A-table row counter (also the record row) restarts; the step counter continues
+    HIPCHK(launch_fill_int(c->d_ctrs, 0, 1, c->stream));
+    const StepTarget t{c->d_insts_scr, A_dev, nullptr, j_dev, n_steps, c->d_ctrs};
+    for (int s = 0; s < n_steps; ++s) CHK(enqueue_step(c, t));
+    c->steps_done += n_steps;
+    c->noalloc_steps = true;
     CHK(sync_out(c));
     return TDKS_OK;
 }
@@ -1434,6 +1519,7 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
     HIPCHK(launch_fill_int(c->d_ctrs, 0, 3, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->steps_done = 0;
+    c->noalloc_steps = false;
     CHK(sync_out(c));
     if (status) return fail(TDKS_E_NUMERIC, "orthonormalisation met linearly dependent bands");
     return TDKS_OK;
@@ -1444,6 +1530,9 @@ int tdks_current(tdks_ctx *c, int mode, double *out, size_t cap, size_t *n_writt
     const size_t ns = size_t(c->steps_done / c->rstride);  // recorded currents
     const size_t rows = (mode == TDKS_PER_GROUP) ? c->groups.size() : size_t(c->n_inst);
     if (mode != TDKS_PER_GROUP && mode != TDKS_PER_INSTANCE) return fail(TDKS_E_ARG, "bad mode");
+    if (c->noalloc_steps)
+        return fail(TDKS_E_STATE, "steps since the load ran through tdks_step_noalloc, whose currents went to the "
+                    "caller's buffer; load again to record");
     if (cap < rows * ns * 3) return fail(TDKS_E_ARG, "capacity %zu < %zu", cap, rows * ns * 3);
     // trace row r of instance i holds J^{(r+1) rstride}
     std::vector<double> tr(size_t(c->n_inst) * 3 * std::max<size_t>(ns, 1));
