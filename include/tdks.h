@@ -114,6 +114,20 @@ typedef struct tdks_instance_desc {
     const double *v_hxc_frozen;  /* HOST [N3][N2][N1], required iff TDKS_HXC_FROZEN */
 } tdks_instance_desc;
 
+/* Tiling of the instances of one shape (an autotuner's result per shape class): applies to
+ * the instances whose grid equals `grid` and whose lattice and band count match; the first
+ * matching rule wins, and fields left 0 fall back to tdks_options.  All instances of one grid
+ * shape and lattice kind share one block size and occupancy target. */
+typedef struct tdks_tiling_rule {
+    int grid[3];          /* N1, N2, N3                                             */
+    int nonorth;          /* 1 non-orthogonal lattices, 0 orthogonal, -1 either     */
+    int n_bands;          /* band count it applies to, 0 any                         */
+    int block_size;       /* threads per workgroup (0 = automatic)                   */
+    int waves_per_simd;   /* 2 or 4 (0 = automatic)                                  */
+    int bands_per_group;  /* bands per workgroup (0 = all)                           */
+    int k_per_group;      /* k-points per workgroup (0 = automatic)                  */
+} tdks_tiling_rule;
+
 typedef void *(*tdks_alloc_fn)(size_t bytes, void *user);
 typedef void (*tdks_free_fn)(void *ptr, void *user);
 
@@ -138,6 +152,9 @@ typedef struct tdks_options {
     int norm_stride;      /* per-orbital norm check every norm_stride steps (0 = off;
                              the charge is checked every step regardless)          */
     int record_stride;    /* record the current every record_stride-th step (0 = 1) */
+    const tdks_tiling_rule *tiling_rules; /* HOST [n_tiling_rules], read by tdks_create only;
+                                             per-shape overrides of the fields above    */
+    int n_tiling_rules;
 } tdks_options;
 
 typedef struct tdks_ctx tdks_ctx;
@@ -156,7 +173,8 @@ void tdks_default_options(tdks_options *opt);
  * support entries, a grid whose orbital and projector tables do not fit the
  * 160 KB of LDS of one workgroup at the requested precision -- FP64 on 20^3,
  * for instance --, taylor_order != 4).  All of these are detected on the host
- * before any device call. */
+ * before any device call.  E_ARG also for tiling rules that give one shape class two
+ * different block sizes or occupancy targets. */
 int tdks_create(const tdks_instance_desc *inst, int n_inst, const tdks_options *opt,
                 tdks_ctx **out);
 
@@ -322,10 +340,10 @@ int tdks_apply_h(tdks_ctx *ctx, int inst, const void *w, void *hw, const double 
  * whole step.  Synchronises.  Same errors as tdks_step. */
 int tdks_time_kernels(tdks_ctx *ctx, int n_steps, const double *A_tab, double *out);
 
-/* Tiling actually used by the first grid shape: threads per workgroup, length of
- * the z-column segment each thread owns, occupancy target (waves per SIMD), bands
- * and k-points per workgroup, and the number of workgroups per step (all
- * shapes).  Outputs may be NULL. */
+/* Tiling actually used by the first grid shape (the first instance's): threads per
+ * workgroup, length of the z-column segment each thread owns, occupancy target (waves
+ * per SIMD), bands and k-points per workgroup (of the first work item), and the number
+ * of workgroups per step (all shapes).  Outputs may be NULL. */
 int tdks_tiling(tdks_ctx *ctx, int *block, int *zl, int *waves_per_simd, int *bands_per_group,
                 int *k_per_group, int *n_groups);
 

@@ -74,7 +74,8 @@ class Propagator:
                  dt: float = 0.02, hxc_mode: str = "scf", v_hxc_frozen: Optional[Sequence] = None,
                  bands_per_group: int = 0, k_per_group: int = 0, block_size: int = 0,
                  graph_steps: int = 16, waves_per_simd: int = 0, use_torch: bool = True,
-                 propagator: str = "taylor", norm_stride: int = 0, record_stride: int = 1):
+                 propagator: str = "taylor", norm_stride: int = 0, record_stride: int = 1,
+                 tiling_rules: Optional[Sequence[dict]] = None):
         self._lib = _lib.load()
         self._ctx = None
         self.n_inst = len(instances)
@@ -125,6 +126,20 @@ class Propagator:
         opt.norm_stride = int(norm_stride)
         opt.record_stride = int(record_stride)
         self.record_stride = max(1, int(record_stride))
+        if tiling_rules:
+            # per-shape tilings (the autotuner's per-class results): grid, nonorth (-1 any),
+            # n_bands (0 any) and the tiling fields, 0 = the context's option
+            rules = (_lib.TilingRule * len(tiling_rules))()
+            for j, r in enumerate(tiling_rules):
+                for q in range(3):
+                    rules[j].grid[q] = int(r["grid"][q])
+                rules[j].nonorth = int(r.get("nonorth", -1))
+                rules[j].n_bands = int(r.get("n_bands", 0))
+                for f in ("block_size", "waves_per_simd", "bands_per_group", "k_per_group"):
+                    setattr(rules[j], f, int(r.get(f, 0)))
+            keep.append(rules)
+            opt.tiling_rules = rules
+            opt.n_tiling_rules = len(tiling_rules)
         self._alloc = None
         self._torch = None
         if use_torch:

@@ -46,6 +46,18 @@ class InstanceDesc(ctypes.Structure):
     ]
 
 
+class TilingRule(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int * 3),
+        ("nonorth", ctypes.c_int),
+        ("n_bands", ctypes.c_int),
+        ("block_size", ctypes.c_int),
+        ("waves_per_simd", ctypes.c_int),
+        ("bands_per_group", ctypes.c_int),
+        ("k_per_group", ctypes.c_int),
+    ]
+
+
 class Options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int),
@@ -64,6 +76,8 @@ class Options(ctypes.Structure):
         ("propagator", ctypes.c_int),
         ("norm_stride", ctypes.c_int),
         ("record_stride", ctypes.c_int),
+        ("tiling_rules", ctypes.POINTER(TilingRule)),
+        ("n_tiling_rules", ctypes.c_int),
     ]
 
 

@@ -7,6 +7,8 @@ timed with HIP events on a sample of the workload (instances of the most common
 grid shape with at least `min_items` k-points in all, so that the sample fills the
 GPU as the workload does) for a few steps; the fastest per update wins.  Results
 are cached in a JSON file keyed by the grid shapes, band counts and precision.
+tune_classes does this per shape class of an uneven batch (grid, lattice kind, band
+count) and returns per-class tiling rules for the library.
 """
 from __future__ import annotations
 
@@ -118,3 +120,37 @@ def tune(instances: Sequence, precision: str = "fp32", steps: int = 3, min_items
         except (OSError, ValueError):
             pass
     return best
+
+
+def _nonorth(inst) -> int:
+    """1 when the lattice rows are not mutually orthogonal (mixed derivatives in the stencil)."""
+    L = np.asarray(inst.lattice, float)
+    G = L @ L.T
+    return int(np.any(np.abs(G - np.diag(np.diag(G))) > 1e-12 * np.max(np.abs(G))))
+
+
+def _class_key(inst):
+    return (tuple(int(g) for g in inst.grid), _nonorth(inst), int(inst.n_bands))
+
+
+def tune_classes(instances: Sequence, precision: str = "fp32", steps: int = 3, min_items: int = 2048,
+                 cache: Optional[str] = DEFAULT_CACHE, verbose: bool = False,
+                 max_candidates: int = 32) -> List[Dict]:
+    """Tunes every shape class of a batch on its own (grid, lattice kind, band count): the
+    instances of the class, as many as it takes to reach `min_items` k-points, are timed
+    under each candidate tiling, and the fastest becomes a tiling rule for that class.
+    Returns the rules for Propagator(..., tiling_rules=...); each class is cached under its
+    own key, so batches that share a class share its result."""
+    groups: Dict = {}
+    for inst in instances:
+        groups.setdefault(_class_key(inst), []).append(inst)
+    rules = []
+    for (grid, nonorth, nb), members in groups.items():
+        opts = tune(members, precision, steps=steps, min_items=min_items, cache=cache, verbose=verbose,
+                    max_candidates=max_candidates)
+        rule = {"grid": list(grid), "nonorth": nonorth, "n_bands": nb}
+        rule.update({k: int(v) for k, v in opts.items()})
+        if verbose:
+            print(f"autotune class grid {grid} nonorth {nonorth} bands {nb}: {rule}")
+        rules.append(rule)
+    return rules

@@ -121,6 +121,7 @@ struct PropArgs {
     int rho_lds;           // accumulate the FP64 density partial in LDS (else in the global slot)
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
+    int mixt;              // non-orthogonal cells: mixed derivatives through the LDS intermediate
     const void *apply_in;  // MODE_APPLY: input orbitals [nk][nb][ng] complex R of instance
     void *apply_out;       // MODE_APPLY: output
 };

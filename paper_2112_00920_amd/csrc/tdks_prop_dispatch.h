@@ -1,20 +1,29 @@
 // Dispatch of the k_propagate instantiations of one translation unit.  The including
-// file defines REAL (float / double), NONORTH_FLAG, ITIME_FLAG (imaginary-time variant)
-// and LAUNCH_NAME; the split lets the variants compile in parallel.
+// file defines REAL (float / double), NONORTH_FLAG (non-orthogonal cells: the kernel's
+// NONORTH is then 1, or 2 with the mixed derivatives through the LDS intermediate when
+// PropArgs::mixt is set), ITIME_FLAG (imaginary-time variant) and LAUNCH_NAME; the split
+// lets the variants compile in parallel.
 #pragma once
 #include "tdks_propagate.h"
 
 namespace tdks {
 
-template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED>
-static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
-    auto kern = k_propagate<REAL, ZL, NONORTH_FLAG, MAXT, MINW, SL, RAGGED, ITIME_FLAG>;
+template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO>
+static hipError_t launch_no(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    auto kern = k_propagate<REAL, ZL, NO, MAXT, MINW, SL, RAGGED, ITIME_FLAG>;
     const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, SL, a, block);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_items), dim3(block), lds, s, a);
     return hipGetLastError();
+}
+
+template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED>
+static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    if (!NONORTH_FLAG) return launch_no<ZL, MAXT, MINW, SL, RAGGED, 0>(a, n_items, block, s);
+    return a.mixt ? launch_no<ZL, MAXT, MINW, SL, RAGGED, 2>(a, n_items, block, s)
+                  : launch_no<ZL, MAXT, MINW, SL, RAGGED, 1>(a, n_items, block, s);
 }
 
 template <bool IT>

@@ -198,14 +198,14 @@ template <> struct PtRec<double> {
 
 // Shared-memory layout of k_propagate (bytes, 16-aligned), identical on host and device.
 struct PropLds {
-    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, nlm, ptp, ptk, rho, total;
+    size_t W, cold, colm, cole, t2m, t2e, apar, part, tsk, atk, ab, wacc, nlm, ptp, ptk, rho, tmix, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
                                             int nmaxd, int nat_max, int ntask_max, int block,
-                                            int rho_lds) {
+                                            int rho_lds, int mixt) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
@@ -229,13 +229,14 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? (fp64 ? 16 : 8) * size_t(nent_max) : 0));  // PtRec records
     L.rho = o; o = al16(o + (rho_lds ? 8 * size_t(ng_max) : 0));  // FP64 density partial
+    L.tmix = o; o = al16(o + (mixt ? c * size_t(ng_max) : 0));      // mixed-derivative intermediate
     L.total = o;
     return L;
 }
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
     return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max,
-                    block, a.rho_lds).total;
+                    block, a.rho_lds, a.mixt).total;
 }
 
 // Uniform real value forced into a scalar register (VALU instructions then read it as
@@ -330,7 +331,12 @@ __device__ __forceinline__ void nl_current(const double *m, double Es, double Ep
     }
 }
 
-template <typename R, int ZL, bool NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME>
+// NONORTH: 0 orthogonal cell (13-point stencil); 1 non-orthogonal, mixed derivatives
+// -sum_{d<e} g_de D1_d D1_e w formed directly (16 neighbours per pair); 2 non-orthogonal with the
+// pairs (0,1) and (0,2) factorised through an LDS intermediate,
+//   -g_01 D1_0 D1_1 w - g_02 D1_0 D1_2 w = D1_0 T,  T = -g_01 D1_1 w - g_02 D1_2 w,
+// formed while the projections run (before their barrier), and the pair (1,2) direct.
+template <typename R, int ZL, int NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -352,7 +358,7 @@ void k_propagate(PropArgs a) {
     const int NW = BS >> 6;
 
     const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd,
-                               a.nat_max, a.ntask_max, BS, a.rho_lds);
+                               a.nat_max, a.ntask_max, BS, a.rho_lds, NONORTH == 2);
     C *W = reinterpret_cast<C *>(smem + L.W);
     Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
     C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
@@ -369,6 +375,7 @@ void k_propagate(PropArgs a) {
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);
     PtRec<R> *ptk_l = reinterpret_cast<PtRec<R> *>(smem + L.ptk);
     double *RHO = reinterpret_cast<double *>(smem + L.rho);
+    C *TM = reinterpret_cast<C *>(smem + L.tmix);
     const bool rho_lds = sizeof(R) == 4 && a.rho_lds != 0;  // the FP64 kernels keep it in HBM
 
     const auto *vtot = gview(reinterpret_cast<const R *>(I.vtot));
@@ -655,6 +662,37 @@ void k_propagate(PropArgs a) {
                         part[4 * t + l] = v;
                     }
                 }
+                if (NONORTH == 2 && active) {
+                    // mixed-derivative intermediate of the owned points, T = cx0 D1_1 w + cx1 D1_2 w
+                    const int pt = opq(pbase);
+                    int oyt[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) oyt[q] = opq(oy[q]);
+#pragma unroll
+                    for (int z = 0; z < ZL; ++z) {
+                        if (!TDKS_ZOK(z)) continue;
+                        const int zg = z0 + z;
+                        const int p = pt + plane * zg;
+                        const C y1 = W[p + oyt[0]], y2 = W[p + oyt[1]], y3 = W[p + oyt[2]], y4 = W[p + oyt[3]];
+                        C zn[4];  // +1, -1, +2, -2 along a_3 (periodic)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int dz = (q == 0) ? 1 : (q == 1) ? -1 : (q == 2) ? 2 : -2;
+                            int zw = zg + dz;
+                            zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
+                            zn[q] = W[pt + plane * zw];
+                        }
+                        C gy, gz;  // D1_1 w, D1_2 w
+                        gy.x = R(D1C1) * (y1.x - y2.x) + R(D1C2) * (y3.x - y4.x);
+                        gy.y = R(D1C1) * (y1.y - y2.y) + R(D1C2) * (y3.y - y4.y);
+                        gz.x = R(D1C1) * (zn[0].x - zn[1].x) + R(D1C2) * (zn[2].x - zn[3].x);
+                        gz.y = R(D1C1) * (zn[0].y - zn[1].y) + R(D1C2) * (zn[2].y - zn[3].y);
+                        C tv;
+                        tv.x = cx[0] * gy.x + cx[1] * gz.x;
+                        tv.y = cx[0] * gy.y + cx[1] * gz.y;
+                        TM[p] = tv;
+                    }
+                }
                 __syncthreads();
                 // scatter coefficients per column image: on the column the non-local term is
                 //   e^{-i kappa.d} sum_lm f_lm(d) E_l c_lm = g conj(t2(j2)) (A + j2 B),
@@ -745,8 +783,16 @@ void k_propagate(PropArgs a) {
                         h.y = fma(-b1[d], p1.x - m1.x, h.y);
                         h.y = fma(-b2[d], p2.x - m2.x, h.y);
                     }
+                    if (NONORTH == 2) {
+                        // pairs (0, 1) and (0, 2): D1_0 T
+                        const C tp1 = TM[p + oxl[0]], tm1 = TM[p + oxl[1]];
+                        const C tp2 = TM[p + oxl[2]], tm2 = TM[p + oxl[3]];
+                        h.x += R(D1C1) * (tp1.x - tm1.x) + R(D1C2) * (tp2.x - tm2.x);
+                        h.y += R(D1C1) * (tp1.y - tm1.y) + R(D1C2) * (tp2.y - tm2.y);
+                    }
                     if (NONORTH) {
-                        // - sum_{d<e} g_de D1_d D1_e w, all from LDS
+                        // - sum_{d<e} g_de D1_d D1_e w, all from LDS (the pair (1, 2) only when the
+                        // others came through T)
                         int oz[4];
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
@@ -756,7 +802,7 @@ void k_propagate(PropArgs a) {
                             oz[s] = plane * (zw - zg);
                         }
 #pragma unroll
-                        for (int q = 0; q < 3; ++q) {
+                        for (int q = (NONORTH == 2 ? 2 : 0); q < 3; ++q) {
                             if (cx[q] == R(0)) continue;
                             C tot;
                             tot.x = R(0);

@@ -133,7 +133,7 @@ struct InstHost {
 struct ShapeClass {
     int N[3];
     bool nonorth;
-    int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0;
+    int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0, mixt = 0;
     int wbeg = 0, wend = 0;
     int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
 };
@@ -538,6 +538,17 @@ int upload(tdks_ctx *c, T **dst, const std::vector<T> &src) {
         if (r_ != TDKS_OK) return r_; \
     } while (0)
 
+// the first tiling rule that applies to an instance, or null
+const tdks_tiling_rule *rule_for(const tdks_options *opt, const InstHost &I) {
+    for (int r = 0; r < opt->n_tiling_rules; ++r) {
+        const tdks_tiling_rule &R = opt->tiling_rules[r];
+        if (R.grid[0] == I.N[0] && R.grid[1] == I.N[1] && R.grid[2] == I.N[2] &&
+            (R.nonorth < 0 || (R.nonorth != 0) == I.nonorth) && (R.n_bands == 0 || R.n_bands == I.nb))
+            return &R;
+    }
+    return nullptr;
+}
+
 // choose the column-segment length, block and occupancy target for one grid shape
 bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl, int &block, int &minw,
                    int &ragged) {
@@ -601,6 +612,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.nent_max = S.nent_max;
     a.nmaxd = S.nmaxd;
     a.rho_lds = S.rho_lds;
+    a.mixt = S.mixt;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
     a.apply_in = nullptr;
@@ -952,6 +964,10 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         return fail(TDKS_E_ARG, "unknown propagator %d", opt->propagator);
     if (opt->norm_stride < 0) return fail(TDKS_E_ARG, "norm_stride must be >= 0");
     if (opt->record_stride < 0) return fail(TDKS_E_ARG, "record_stride must be >= 0");
+    if (opt->n_tiling_rules < 0 || (opt->n_tiling_rules > 0 && !opt->tiling_rules))
+        return fail(TDKS_E_ARG, "bad tiling rules");
+    c->opt.tiling_rules = nullptr;  // borrowed for this call only
+    c->opt.n_tiling_rules = 0;
     c->rstride = opt->record_stride > 0 ? opt->record_stride : 1;
     c->fp64 = opt->precision == TDKS_FP64;
     c->n_inst = n_inst;
@@ -1021,22 +1037,30 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         I.lam0 = kinetic_bound(I) + vmax + c->tables[I.table].nl_bound + 5.0;
         I.lamA = kmax + cs;
     }
-    // shape classes and tiling
+    // shape classes and tiling (per-shape rules override the context's options)
+    std::vector<int> class_block(0), class_waves(0);
     for (int i = 0; i < n_inst; ++i) {
         InstHost &I = c->inst[i];
+        const tdks_tiling_rule *R = rule_for(opt, I);
+        const int want_b = (R && R->block_size > 0) ? R->block_size : opt->block_size;
+        const int want_w = (R && R->waves_per_simd > 0) ? R->waves_per_simd : opt->waves_per_simd;
         int cls = -1;
         for (size_t s = 0; s < c->classes.size(); ++s) {
             const ShapeClass &S = c->classes[s];
             if (S.N[0] == I.N[0] && S.N[1] == I.N[1] && S.N[2] == I.N[2] && S.nonorth == I.nonorth) cls = int(s);
         }
+        if (cls >= 0 && (class_block[cls] != want_b || class_waves[cls] != want_w))
+            return fail(TDKS_E_ARG, "instance %d: its tiling rule gives grid %dx%dx%d another block size or "
+                        "occupancy than an earlier instance of that shape", i, I.N[0], I.N[1], I.N[2]);
         if (cls < 0) {
             ShapeClass S;
             for (int q = 0; q < 3; ++q) S.N[q] = I.N[q];
             S.nonorth = I.nonorth;
-            if (!choose_tiling(S.N, c->fp64, opt->block_size, opt->waves_per_simd, S.zl, S.block, S.minw,
-                               S.ragged))
+            if (!choose_tiling(S.N, c->fp64, want_b, want_w, S.zl, S.block, S.minw, S.ragged))
                 return fail(TDKS_E_UNSUPPORTED, "no built propagation tiling for grid %dx%dx%d", S.N[0], S.N[1], S.N[2]);
             c->classes.push_back(S);
+            class_block.push_back(want_b);
+            class_waves.push_back(want_w);
             cls = int(c->classes.size()) - 1;
         }
         I.cls = cls;
@@ -1055,13 +1079,22 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     }
     for (ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
-        // FP32: stage the point-major projector tables in LDS when they fit; then keep the
-        // density partial in LDS too if there is room (in the global slot, every band's
-        // update of it would leave L2)
-        S.sl = (!c->fp64 && propagate_lds_bytes(c->fp64, 1, a, S.block) <= 160 * 1024) ? 1 : 0;
-        a.rho_lds = 1;
-        S.rho_lds = (!c->fp64 && propagate_lds_bytes(c->fp64, S.sl, a, S.block) <= 160 * 1024) ? 1 : 0;
+        auto fits = [&](int sl, int rho, int mixt) {
+            a.rho_lds = rho;
+            a.mixt = mixt;
+            return propagate_lds_bytes(c->fp64, sl, a, S.block) <= 160 * 1024;
+        };
+        // non-orthogonal cells: the mixed-derivative intermediate when it fits beside the
+        // orbital and the LDS-staged projector records (FP32), at the expense of the density
+        // partial if need be; FP32: stage the point-major projector tables in LDS when they
+        // fit; then keep the density partial in LDS too if there is room (in the global slot,
+        // every band's update of it would leave L2)
+        S.mixt = (S.nonorth && fits(c->fp64 ? 0 : 1, 0, 1)) ? 1 : 0;
+        if (S.nonorth && !S.mixt && !c->fp64 && fits(0, 0, 1)) S.mixt = 1;
+        S.sl = (!c->fp64 && fits(1, 0, S.mixt)) ? 1 : 0;
+        S.rho_lds = (!c->fp64 && fits(S.sl, 1, S.mixt)) ? 1 : 0;
         a.rho_lds = S.rho_lds;
+        a.mixt = S.mixt;
         const size_t lds = propagate_lds_bytes(c->fp64, S.sl, a, S.block);
         if (lds > 160 * 1024)
             return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of LDS per workgroup", S.N[0], S.N[1],
@@ -1071,7 +1104,9 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     long long items1 = 0;  // work items with one k-point per workgroup
     for (int i = 0; i < n_inst; ++i) {
         const InstHost &I = c->inst[i];
-        const int bpg = (opt->bands_per_group > 0 && opt->bands_per_group < I.nb) ? opt->bands_per_group : I.nb;
+        const tdks_tiling_rule *R = rule_for(opt, I);
+        const int want = (R && R->bands_per_group > 0) ? R->bands_per_group : opt->bands_per_group;
+        const int bpg = (want > 0 && want < I.nb) ? want : I.nb;
         items1 += (long long)I.nk * ((I.nb + bpg - 1) / bpg);
     }
     const bool big = items1 >= 16384;
@@ -1081,12 +1116,15 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         for (int i = 0; i < n_inst; ++i) {
             InstHost &I = c->inst[i];
             if (I.cls != int(s)) continue;
-            const int bpg = (opt->bands_per_group > 0 && opt->bands_per_group < I.nb) ? opt->bands_per_group : I.nb;
+            const tdks_tiling_rule *R = rule_for(opt, I);
+            const int want = (R && R->bands_per_group > 0) ? R->bands_per_group : opt->bands_per_group;
+            const int bpg = (want > 0 && want < I.nb) ? want : I.nb;
+            const int want_k = (R && R->k_per_group > 0) ? R->k_per_group : opt->k_per_group;
             // k-points per workgroup: by default 4 for instances with at least 256 k-points in
             // a context of at least 16384 single-k work items (64 per CU: fewer table stagings
             // and density slots, 2.5 % faster per step on the two-step workload), else 1 (a
             // lone 512-k instance needs its 512 workgroups to fill the GPU)
-            const int kpg = opt->k_per_group > 0 ? opt->k_per_group : (I.nk >= 256 && big ? 4 : 1);
+            const int kpg = want_k > 0 ? want_k : (I.nk >= 256 && big ? 4 : 1);
             I.wbeg = int(c->work.size());
             int slot = 0;
             for (int k0 = 0; k0 < I.nk; k0 += kpg)

@@ -50,6 +50,8 @@ int main(void) {
          offsetof(tdks_options, waves_per_simd));
   printf("%zu %zu %zu\\n", offsetof(tdks_options, propagator), offsetof(tdks_options, norm_stride),
          offsetof(tdks_options, record_stride));
+  printf("%zu %zu %zu %zu\\n", offsetof(tdks_options, tiling_rules), offsetof(tdks_options, n_tiling_rules),
+         sizeof(tdks_tiling_rule), offsetof(tdks_tiling_rule, k_per_group));
   return 0;
 }
 """)
@@ -62,6 +64,8 @@ int main(void) {
     assert vals[7:12] == [O.stream.offset, O.alloc_user.offset, O.block_size.offset, O.graph_steps.offset,
                           O.waves_per_simd.offset]
     assert vals[12:15] == [O.propagator.offset, O.norm_stride.offset, O.record_stride.offset]
+    assert vals[15:19] == [O.tiling_rules.offset, O.n_tiling_rules.offset, ctypes.sizeof(_lib.TilingRule),
+                           _lib.TilingRule.k_per_group.offset]
 
 
 def test_default_options():
@@ -131,3 +135,34 @@ def test_argument_errors_before_device_work(case):
     assert rc == want, lib.tdks_last_error()
     assert ctx.value is None
     assert len(lib.tdks_last_error()) > 0
+
+
+def test_tiling_rule_errors_before_device_work():
+    """Rules that give one shape class two block sizes, and a rule count without rules, are
+    argument errors found on the host."""
+    lib = _lib.load()
+    sp = W.Species(D=-1.0, w=1.0, Rc=3.5)
+    insts = [W.make_instance("diamond8", (8, 8, 8), nb, [sp], W.KSpec((1, 1, 1))) for nb in (2, 3)]
+    descs = (_lib.InstanceDesc * 2)()
+    keep = []
+    for i, inst in enumerate(insts):
+        d, k = _desc(inst, np.zeros((1, 3)))
+        descs[i] = d
+        keep.append(k)
+    opt = _lib.Options()
+    lib.tdks_default_options(ctypes.byref(opt))
+    rules = (_lib.TilingRule * 2)()
+    for j, (nb, blk) in enumerate([(2, 512), (3, 256)]):
+        rules[j].grid[:] = [8, 8, 8]
+        rules[j].nonorth = -1
+        rules[j].n_bands = nb
+        rules[j].block_size = blk
+    opt.tiling_rules = rules
+    opt.n_tiling_rules = 2
+    ctx = ctypes.c_void_p()
+    assert lib.tdks_create(descs, 2, ctypes.byref(opt), ctypes.byref(ctx)) == _lib.E_ARG
+    assert b"another block size" in lib.tdks_last_error()
+    opt.tiling_rules = None
+    opt.n_tiling_rules = 1
+    assert lib.tdks_create(descs, 2, ctypes.byref(opt), ctypes.byref(ctx)) == _lib.E_ARG
+    assert ctx.value is None
