@@ -140,7 +140,9 @@ typedef struct tdks_options {
     tdks_alloc_fn alloc;  /* device allocator, or NULL for hipMalloc               */
     tdks_free_fn free;    /* matching free, or NULL for hipFree                    */
     void *alloc_user;     /* passed to alloc/free                                  */
-    int bands_per_group;  /* bands propagated by one workgroup (0 = all)           */
+    int bands_per_group;  /* bands propagated by one workgroup (0 = all, or, for a
+                             grid shape with fewer work items than the GPU's 256
+                             compute units, the bands split in halves down to 8)  */
     int k_per_group;      /* k-points per workgroup (0 = 4 for instances with at
                              least 256 k-points when the context has at least
                              16384 (k, band group) items, else 1)                 */
@@ -170,9 +172,10 @@ void tdks_default_options(tdks_options *opt);
  * Errors: E_ARG (bad descriptor, e.g. Rc too large for the cell), E_OOM,
  * E_HIP, E_UNSUPPORTED (an axis outside 4..32 points or more than 8192 grid
  * points, more than 64 atoms, more than 4095 projector column images or 65535
- * support entries, a grid whose orbital and projector tables do not fit the
- * 160 KB of LDS of one workgroup at the requested precision -- FP64 on 20^3,
- * for instance --, taylor_order != 4).  All of these are detected on the host
+ * support entries, a grid whose orbital does not fit the 160 KB of LDS of one
+ * workgroup beside its small tables, taylor_order != 4).  FP64 grids whose
+ * per-column-image tables do not fit beside the orbital (20^3, 16x16x32) keep those
+ * tables in device memory, one slice per work item (a slower path).  All of these are detected on the host
  * before any device call.  E_ARG also for tiling rules that give one shape class two
  * different block sizes or occupancy targets. */
 int tdks_create(const tdks_instance_desc *inst, int n_inst, const tdks_options *opt,

@@ -122,6 +122,8 @@ struct PropArgs {
     int nat_max;           // most atoms of an instance in the launch
     int ntask_max;         // most projection tasks of an instance in the launch
     int mixt;              // non-orthogonal cells: mixed derivatives through the LDS intermediate
+    char *gcol;            // per-work-item global column tables of the launch (FP64 grids whose tables
+                           // do not fit the LDS beside the orbital), or null
     const void *apply_in;  // MODE_APPLY: input orbitals [nk][nb][ng] complex R of instance
     void *apply_out;       // MODE_APPLY: output
 };
@@ -130,6 +132,7 @@ struct PropArgs {
 hipError_t launch_propagate(int fp64, const PropArgs &a, int n_items, int block, int zl, int minw,
                             int nonorth, int sl, int ragged, hipStream_t s);
 size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block);
+size_t propagate_gcol_stride(int fp64, int ncol_max);  // bytes of one work item's global column tables
 bool propagate_config_ok(int block, int zl, int minw, int ragged);
 hipError_t launch_reduce(const DevInst *insts, int inst0, int n, int ng_max, double *rho,
                          double *jout, int jstride, const int *step_ctr, const HealthArgs &h, hipStream_t s);

@@ -17,6 +17,8 @@ size_t propagate_lds_bytes(int fp64, int sl, const PropArgs &a, int block) {
     return propagate_lds_bytes_inl(fp64, sl, a, block);
 }
 
+size_t propagate_gcol_stride(int fp64, int ncol_max) { return prop_gcol(fp64, ncol_max).stride; }
+
 bool propagate_config_ok(int block, int zl, int minw, int ragged) {
     if (block < 64 || block > 1024 || (block & 63)) return false;
 #define TDKS_OK_CASE(Z, M, O) if (zl == Z && block <= M && minw == O) return true;

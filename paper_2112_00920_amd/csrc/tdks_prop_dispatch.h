@@ -8,15 +8,25 @@
 
 namespace tdks {
 
-template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO>
-static hipError_t launch_no(const PropArgs &a, int n_items, int block, hipStream_t s) {
-    auto kern = k_propagate<REAL, ZL, NO, MAXT, MINW, SL, RAGGED, ITIME_FLAG>;
+template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO, bool GC>
+static hipError_t launch_gc(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    auto kern = k_propagate<REAL, ZL, NO, MAXT, MINW, SL, RAGGED, ITIME_FLAG, GC>;
     const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, SL, a, block);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(n_items), dim3(block), lds, s, a);
     return hipGetLastError();
+}
+
+// the global column tables are built for FP64 only (the FP32 tables fit the LDS)
+template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO>
+static hipError_t launch_no(const PropArgs &a, int n_items, int block, hipStream_t s) {
+    if constexpr (sizeof(REAL) == 8 && !SL) {
+        if (a.gcol) return launch_gc<ZL, MAXT, MINW, SL, RAGGED, NO, true>(a, n_items, block, s);
+    }
+    if (a.gcol) return hipErrorInvalidValue;
+    return launch_gc<ZL, MAXT, MINW, SL, RAGGED, NO, false>(a, n_items, block, s);
 }
 
 template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED>

@@ -203,13 +203,16 @@ struct PropLds {
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// With gcol the per-column-image tables (geometry, the two phase tables, the scatter
+// coefficients) live in a per-workgroup global buffer instead (prop_gcol), so that FP64
+// orbitals of grids up to 8192 points fit the LDS.
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
                                             int nmaxd, int nat_max, int ntask_max, int block,
-                                            int rho_lds, int mixt) {
+                                            int rho_lds, int mixt, int gcol = 0) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
-    const int nc = ncol_max > 0 ? ncol_max : 1;
+    const int nc = gcol ? 0 : (ncol_max > 0 ? ncol_max : 1);
     PropLds L;
     size_t o = 0;
     L.W = o; o = al16(o + c * size_t(ng_max));
@@ -236,7 +239,25 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
     return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max,
-                    block, a.rho_lds, a.mixt).total;
+                    block, a.rho_lds, a.mixt, a.gcol != nullptr).total;
+}
+
+// Layout of one workgroup's global column tables (bytes, 256-aligned stride): geometry, phase
+// at the mid-step, phase at the step's end, scatter coefficients.
+struct PropGcol {
+    size_t cold, colm, cole, ab, stride;
+};
+__host__ __device__ inline PropGcol prop_gcol(int fp64, int ncol_max) {
+    const size_t c = fp64 ? 16 : 8, r = fp64 ? 8 : 4;
+    const size_t nc = ncol_max > 0 ? size_t(ncol_max) : 1;
+    PropGcol G;
+    size_t o = 0;
+    G.cold = o; o = al16(o + 4 * r * nc);
+    G.colm = o; o = al16(o + c * nc);
+    G.cole = o; o = al16(o + c * nc);
+    G.ab = o; o = al16(o + 2 * c * nc);
+    G.stride = (o + 255) & ~size_t(255);
+    return G;
 }
 
 // Uniform real value forced into a scalar register (VALU instructions then read it as
@@ -336,7 +357,9 @@ __device__ __forceinline__ void nl_current(const double *m, double Es, double Ep
 // pairs (0,1) and (0,2) factorised through an LDS intermediate,
 //   -g_01 D1_0 D1_1 w - g_02 D1_0 D1_2 w = D1_0 T,  T = -g_01 D1_1 w - g_02 D1_2 w,
 // formed while the projections run (before their barrier), and the pair (1,2) direct.
-template <typename R, int ZL, int NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME>
+// GC: the per-column-image tables in the work item's part of a.gcol (global memory, read and
+// written only by this workgroup, ordered by its barriers) instead of LDS.
+template <typename R, int ZL, int NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME, bool GC = false>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -358,18 +381,20 @@ void k_propagate(PropArgs a) {
     const int NW = BS >> 6;
 
     const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd,
-                               a.nat_max, a.ntask_max, BS, a.rho_lds, NONORTH == 2);
+                               a.nat_max, a.ntask_max, BS, a.rho_lds, NONORTH == 2, GC);
+    const PropGcol G = prop_gcol(sizeof(R) == 8, a.ncol_max);
+    char *gcb = GC ? a.gcol + size_t(blockIdx.x) * G.stride : nullptr;
     C *W = reinterpret_cast<C *>(smem + L.W);
-    Q4 *cold = reinterpret_cast<Q4 *>(smem + L.cold);       // dcol.xyz, atom index
-    C *colm = reinterpret_cast<C *>(smem + L.colm);         // column phase, kappa(t_n + dt/2)
-    C *cole = reinterpret_cast<C *>(smem + L.cole);         // column phase, kappa(t_{n+1})
+    Q4 *cold = reinterpret_cast<Q4 *>(GC ? gcb + G.cold : smem + L.cold);  // dcol.xyz, atom index
+    C *colm = reinterpret_cast<C *>(GC ? gcb + G.colm : smem + L.colm);    // column phase, kappa(t_n + dt/2)
+    C *cole = reinterpret_cast<C *>(GC ? gcb + G.cole : smem + L.cole);    // column phase, kappa(t_{n+1})
     C *t2m = reinterpret_cast<C *>(smem + L.t2m);           // e^{i j2 kappa.a_3/N3}, mid
     C *t2e = reinterpret_cast<C *>(smem + L.t2e);           // same, kappa(t_{n+1})
     Q4 *apar = reinterpret_cast<Q4 *>(smem + L.apar);       // Es dV, Ep dV, Ns, Np per atom
     C *part = reinterpret_cast<C *>(smem + L.part);
     int2 *task_l = reinterpret_cast<int2 *>(smem + L.tsk);
     int *atk_l = reinterpret_cast<int *>(smem + L.atk);
-    Q4 *AB = reinterpret_cast<Q4 *>(smem + L.ab);           // scatter coefficients A, B per column image
+    Q4 *AB = reinterpret_cast<Q4 *>(GC ? gcb + G.ab : smem + L.ab);  // scatter coefficients A, B per column image
     double *wacc = reinterpret_cast<double *>(smem + L.wacc);  // current partial per wave (x, y, z, -)
     double *nlm = reinterpret_cast<double *>(smem + L.nlm);    // non-local current moments per task
     uint16_t *ptp_l = reinterpret_cast<uint16_t *>(smem + L.ptp);

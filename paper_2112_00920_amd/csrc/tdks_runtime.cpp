@@ -134,6 +134,9 @@ struct ShapeClass {
     int N[3];
     bool nonorth;
     int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0, mixt = 0;
+    int gc = 0;                 // FP64 column tables in global memory (grids beyond the LDS otherwise)
+    char *gcol = nullptr;       // their buffer, one slice of gstride bytes per work item of the class
+    size_t gstride = 0;
     int wbeg = 0, wend = 0;
     int ng_max = 0, ncol_max = 0, nent_max = 0, nmaxd = 0, nat_max = 0, ntask_max = 0;
 };
@@ -599,6 +602,13 @@ int sync_out(tdks_ctx *c) {
     return TDKS_OK;
 }
 
+// the launch covers the class's work items from wb on: their instance table, work list and
+// global column-table slices
+void set_work(tdks_ctx *c, const ShapeClass &S, int wb, PropArgs &a) {
+    a.work = c->d_work + wb;
+    if (a.gcol) a.gcol = S.gcol + size_t(wb - S.wbeg) * S.gstride;
+}
+
 PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A, const int *ctr) {
     PropArgs a;
     a.insts = c->d_insts;
@@ -613,6 +623,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.nmaxd = S.nmaxd;
     a.rho_lds = S.rho_lds;
     a.mixt = S.mixt;
+    a.gcol = S.gcol;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
     a.apply_in = nullptr;
@@ -664,7 +675,7 @@ int enqueue_propagation(tdks_ctx *c, int mode, const StepTarget &t) {
     return for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
         PropArgs a = class_args(c, S, mode, t.A, c->d_ctrs);
         a.insts = t.insts;
-        a.work = c->d_work + S.wbeg;
+        set_work(c, S, S.wbeg, a);
         HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
         return TDKS_OK;
     });
@@ -802,7 +813,7 @@ int enqueue_observe(tdks_ctx *c, int i_first, int i_last, double *jdst, int set_
         }
         if (we <= wb) return TDKS_OK;
         PropArgs a = class_args(c, S, mode, c->d_Aobs, c->d_ctrs + 2);
-        a.work = c->d_work + wb;
+        set_work(c, S, wb, a);
         HIPCHK(launch_propagate(c->fp64, a, we - wb, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged, st));
         return TDKS_OK;
     }));
@@ -1079,9 +1090,10 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     }
     for (ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
-        auto fits = [&](int sl, int rho, int mixt) {
+        auto fits = [&](int sl, int rho, int mixt, int gc = 0) {
             a.rho_lds = rho;
             a.mixt = mixt;
+            a.gcol = gc ? reinterpret_cast<char *>(256) : nullptr;  // only its presence counts here
             return propagate_lds_bytes(c->fp64, sl, a, S.block) <= 160 * 1024;
         };
         // non-orthogonal cells: the mixed-derivative intermediate when it fits beside the
@@ -1093,8 +1105,14 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         if (S.nonorth && !S.mixt && !c->fp64 && fits(0, 0, 1)) S.mixt = 1;
         S.sl = (!c->fp64 && fits(1, 0, S.mixt)) ? 1 : 0;
         S.rho_lds = (!c->fp64 && fits(S.sl, 1, S.mixt)) ? 1 : 0;
+        // FP64 grids whose orbital and column tables exceed the LDS (20^3, 16x16x32): the
+        // column tables go to a per-work-item global buffer
+        S.gc = (c->fp64 && !fits(0, 0, S.mixt) && fits(0, 0, 0, 1)) ? 1 : 0;
+        if (S.gc) S.mixt = 0;
         a.rho_lds = S.rho_lds;
         a.mixt = S.mixt;
+        a.gcol = S.gc ? reinterpret_cast<char *>(256) : nullptr;
+        S.gstride = S.gc ? propagate_gcol_stride(c->fp64, S.ncol_max) : 0;
         const size_t lds = propagate_lds_bytes(c->fp64, S.sl, a, S.block);
         if (lds > 160 * 1024)
             return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d needs %zu bytes of LDS per workgroup", S.N[0], S.N[1],
@@ -1110,6 +1128,15 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         items1 += (long long)I.nk * ((I.nb + bpg - 1) / bpg);
     }
     const bool big = items1 >= 16384;
+    // work items of each shape class with every band in one workgroup
+    std::vector<long long> class_items(c->classes.size(), 0);
+    for (int i = 0; i < n_inst; ++i) {
+        const InstHost &I = c->inst[i];
+        const tdks_tiling_rule *R = rule_for(opt, I);
+        const int want = (R && R->bands_per_group > 0) ? R->bands_per_group : opt->bands_per_group;
+        const int bpg = (want > 0 && want < I.nb) ? want : I.nb;
+        class_items[I.cls] += (long long)I.nk * ((I.nb + bpg - 1) / bpg);
+    }
     for (size_t s = 0; s < c->classes.size(); ++s) {
         ShapeClass &S = c->classes[s];
         S.wbeg = int(c->work.size());
@@ -1118,7 +1145,15 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
             if (I.cls != int(s)) continue;
             const tdks_tiling_rule *R = rule_for(opt, I);
             const int want = (R && R->bands_per_group > 0) ? R->bands_per_group : opt->bands_per_group;
-            const int bpg = (want > 0 && want < I.nb) ? want : I.nb;
+            int bpg = (want > 0 && want < I.nb) ? want : I.nb;
+            // a class with fewer work items than compute units (a lone small-k instance, the
+            // 13 supercells of the uneven batch) splits its bands, down to 8 per workgroup, until
+            // its items cover the 256 CUs (the supercell class alone: 1.84 -> 1.06 ms)
+            if (want <= 0) {
+                int f = 1;
+                while (class_items[s] * f < 256 && (I.nb + 2 * f - 1) / (2 * f) >= 8) f *= 2;
+                bpg = (I.nb + f - 1) / f;
+            }
             const int want_k = (R && R->k_per_group > 0) ? R->k_per_group : opt->k_per_group;
             // k-points per workgroup: by default 4 for instances with at least 256 k-points in
             // a context of at least 16384 single-k work items (64 per CU: fewer table stagings
@@ -1315,6 +1350,12 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         if (off <= kScratchBytes) CHK(upload(c, &c->d_insts_scr, scr));
     }
     CHK(upload(c, &c->d_work, c->work));
+    for (ShapeClass &S : c->classes) {
+        if (!S.gc) continue;
+        const size_t bytes = S.gstride * size_t(S.wend - S.wbeg);
+        S.gcol = static_cast<char *>(c->alloc(bytes));
+        if (!S.gcol) return fail(TDKS_E_OOM, "column-table allocation of %zu bytes failed", bytes);
+    }
     HIPCHK(launch_vtot(c->d_insts, 0, n_inst, c->ng_max, c->d_vloc, c->d_vhxc, c->d_vtot, c->fp64, c->stream));
     c->jpre.assign(3 * n_inst, 0.0);
     CHK(ensure_A(c, 64));
@@ -1431,6 +1472,10 @@ int tdks_step_noalloc(tdks_ctx *c, int n_steps, const double *A_dev, double *j_d
     if (c->scratch_need > kScratchBytes)
         return fail(TDKS_E_UNSUPPORTED, "the partial sums of this context need %zu bytes; the static scratch array "
                     "holds %zu (use tdks_step)", c->scratch_need, kScratchBytes);
+    for (const ShapeClass &S : c->classes)
+        if (S.gc)
+            return fail(TDKS_E_UNSUPPORTED, "grid %dx%dx%d keeps its FP64 column tables in context memory outside "
+                        "the scratch array (use tdks_step)", S.N[0], S.N[1], S.N[2]);
     if (n_steps == 0) return TDKS_OK;
     if (!A_dev || !j_dev) return fail(TDKS_E_ARG, "null A table or current buffer");
     for (int i = 0; i < c->n_inst; ++i)
@@ -1525,7 +1570,7 @@ int tdks_ground_state(tdks_ctx *c, int n_iter, double tau, double mix, double *r
         CHK(for_classes(c, [&](const ShapeClass &S, hipStream_t st) {
             PropArgs a = class_args(c, S, MODE_ITIME, c->d_Aobs, c->d_ctrs + 2);
             a.dt = tau;
-            a.work = c->d_work + S.wbeg;
+            set_work(c, S, S.wbeg, a);
             HIPCHK(launch_propagate(c->fp64, a, S.wend - S.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,
                                     st));
             return TDKS_OK;
@@ -1704,7 +1749,7 @@ int tdks_apply_h(tdks_ctx *c, int i, const void *w, void *hw, const double *A, i
     HIPCHK(hipMemcpyAsync(c->d_Aobs, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
     const ShapeClass &S = c->classes[I.cls];
     PropArgs a = class_args(c, S, MODE_APPLY, c->d_Aobs, c->d_ctrs + 2);
-    a.work = c->d_work + I.wbeg;
+    set_work(c, S, I.wbeg, a);
     a.apply_in = win;
     a.apply_out = wout;
     HIPCHK(launch_propagate(c->fp64, a, I.wend - I.wbeg, S.block, S.zl, S.minw, S.nonorth, S.sl, S.ragged,

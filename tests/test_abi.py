@@ -98,7 +98,7 @@ def _desc(inst, k):
 
 
 @pytest.mark.parametrize("case", ["rc_too_large", "bad_order", "no_bands", "grid_too_big", "bad_species",
-                                  "fp64_lds", "axis_too_small", "norm_stride", "record_stride"])
+                                  "no_tiling", "axis_too_small", "norm_stride", "record_stride"])
 def test_argument_errors_before_device_work(case):
     lib = _lib.load()
     sp = W.Species(D=-1.0, w=1.0, Rc=3.5)
@@ -109,8 +109,8 @@ def test_argument_errors_before_device_work(case):
         cell = "fcc2"
     if case == "grid_too_big":
         grid = (64, 64, 64)
-    if case == "fp64_lds":  # a 20^3 FP64 orbital and its tables exceed the LDS of a workgroup
-        grid = (20, 20, 20)
+    if case == "no_tiling":  # 704 columns of 11 points: no built z-segment gives <= 1024 threads
+        grid = (32, 22, 11)
     if case == "axis_too_small":
         grid = (8, 8, 3)
     inst = W.make_instance(cell, grid, 0 if case == "no_bands" else 2, [sp], W.KSpec((1, 1, 1)))
@@ -130,7 +130,7 @@ def test_argument_errors_before_device_work(case):
     ctx = ctypes.c_void_p()
     rc = lib.tdks_create(ctypes.byref(d), 1, ctypes.byref(opt), ctypes.byref(ctx))
     want = {"rc_too_large": _lib.E_ARG, "bad_order": _lib.E_UNSUPPORTED, "no_bands": _lib.E_ARG,
-            "grid_too_big": _lib.E_UNSUPPORTED, "bad_species": _lib.E_ARG, "fp64_lds": _lib.E_UNSUPPORTED,
+            "grid_too_big": _lib.E_UNSUPPORTED, "bad_species": _lib.E_ARG, "no_tiling": _lib.E_UNSUPPORTED,
             "axis_too_small": _lib.E_UNSUPPORTED, "norm_stride": _lib.E_ARG, "record_stride": _lib.E_ARG}[case]
     assert rc == want, lib.tdks_last_error()
     assert ctx.value is None

@@ -6,7 +6,8 @@
   golden induced currents of tests/golden (written by make_golden.py with the oracle):
   the plain 512-k instance, one two-step sub-simulation (512 k), one HHG sub-simulation on
   20^3 at the peak of the pulse (64 k), and one instance of each kind of the uneven batch.
-  FP64 where the grid fits the FP64 kernel's LDS, FP32 everywhere.
+  FP64 and FP32 each (on 20^3 and 16x16x32 the FP64 kernel keeps its per-column-image
+  tables in device memory).
 * The two-step batch in FP64 at full size in the benchmark's FP64 tiling (4 k-points per
   workgroup), sampled against the oracle, and the 4-k grouping against 1-k grouping.
 
@@ -84,11 +85,11 @@ def test_c1_full_length(tdks, c1_oracle, precision):
 GOLDEN = {
     "c2_plain_g16_mp8": ("fp64", "fp32"),
     "c3_twostep_sub27": ("fp64", "fp32"),
-    "c4_hhg_sub21_peak": ("fp32",),  # 20^3: the FP64 kernel's orbital and tables exceed the LDS
+    "c4_hhg_sub21_peak": ("fp64", "fp32"),  # 20^3: FP64 with the column tables in device memory
     "c5_uneven_fcc2": ("fp64", "fp32"),
     "c5_uneven_cubic16": ("fp64", "fp32"),
-    "c5_uneven_cubic20": ("fp32",),
-    "c5_uneven_super16": ("fp32",),  # 16x16x32: same
+    "c5_uneven_cubic20": ("fp64", "fp32"),
+    "c5_uneven_super16": ("fp64", "fp32"),  # 16x16x32: same
 }
 
 

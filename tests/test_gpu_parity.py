@@ -47,6 +47,8 @@ CASES = {
     "fcc2_8": ("fcc2", (8, 8, 8), 3, W.KSpec((2, 2, 1))),
     "s16_8x8x16": ("super16", (8, 8, 16), 3, W.KSpec((1, 1, 2))),
     "d8_16": ("diamond8", (16, 16, 16), 2, W.KSpec((1, 1, 2))),
+    # FP64: the per-column-image tables in device memory (they do not fit the LDS beside the orbital)
+    "d8_20": ("diamond8", (20, 20, 20), 2, W.KSpec((1, 2, 1))),
 }
 
 
@@ -99,6 +101,8 @@ STEP_CASES = {
     "fcc2_8": ("fcc2", (8, 8, 8), 3, W.KSpec((2, 2, 2)), 6, {}),
     "s16_8x8x16": ("super16", (8, 8, 16), 6, W.KSpec((1, 1, 2)), 4, {}),
     "d8_16": ("diamond8", (16, 16, 16), 3, W.KSpec((1, 1, 2)), 4, {}),
+    "s16_16x16x32": ("super16", (16, 16, 32), 2, W.KSpec((1, 1, 2)), 3, {}),
+    "d8_20_split_bands": ("diamond8", (20, 20, 20), 16, W.KSpec((1, 1, 1)), 3, {}),
 }
 
 
