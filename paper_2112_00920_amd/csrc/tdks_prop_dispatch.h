@@ -8,10 +8,10 @@
 
 namespace tdks {
 
-template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO, bool GC>
+template <int ZL, int MAXT, int MINW, int SL, bool RAGGED, int NO, bool GC>
 static hipError_t launch_gc(const PropArgs &a, int n_items, int block, hipStream_t s) {
     auto kern = k_propagate<REAL, ZL, NO, MAXT, MINW, SL, RAGGED, ITIME_FLAG, GC>;
-    const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, SL, a, block);
+    const size_t lds = propagate_lds_bytes_inl(sizeof(REAL) == 8, SL == 1, a, block);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
@@ -20,16 +20,16 @@ static hipError_t launch_gc(const PropArgs &a, int n_items, int block, hipStream
 }
 
 // the global column tables are built for FP64 only (the FP32 tables fit the LDS)
-template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED, int NO>
+template <int ZL, int MAXT, int MINW, int SL, bool RAGGED, int NO>
 static hipError_t launch_no(const PropArgs &a, int n_items, int block, hipStream_t s) {
-    if constexpr (sizeof(REAL) == 8 && !SL) {
+    if constexpr (sizeof(REAL) == 8 && SL != 1) {
         if (a.gcol) return launch_gc<ZL, MAXT, MINW, SL, RAGGED, NO, true>(a, n_items, block, s);
     }
     if (a.gcol) return hipErrorInvalidValue;
     return launch_gc<ZL, MAXT, MINW, SL, RAGGED, NO, false>(a, n_items, block, s);
 }
 
-template <int ZL, int MAXT, int MINW, bool SL, bool RAGGED>
+template <int ZL, int MAXT, int MINW, int SL, bool RAGGED>
 static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream_t s) {
     if (!NONORTH_FLAG) return launch_no<ZL, MAXT, MINW, SL, RAGGED, 0>(a, n_items, block, s);
     return a.mixt ? launch_no<ZL, MAXT, MINW, SL, RAGGED, 2>(a, n_items, block, s)
@@ -41,8 +41,9 @@ static hipError_t dispatch(const PropArgs &a, int n_items, int block, int zl, in
                            hipStream_t s) {
 #define TDKS_CASE(Z, M, O, RG)                                                                      \
     if (ragged == RG && zl == Z && block <= M && minw == O) {                                       \
-        return sl ? launch_zl<Z, M, O, true, RG>(a, n_items, block, s)                              \
-                  : launch_zl<Z, M, O, false, RG>(a, n_items, block, s);                            \
+        return sl ? launch_zl<Z, M, O, 1, RG>(a, n_items, block, s)                                 \
+                  : a.ptp_lds ? launch_zl<Z, M, O, 2, RG>(a, n_items, block, s)                     \
+                              : launch_zl<Z, M, O, 0, RG>(a, n_items, block, s);                    \
     }
 #define TDKS_CASE_EVEN(Z, M, O) TDKS_CASE(Z, M, O, false)
 #define TDKS_CASE_RAGGED(Z, M, O) TDKS_CASE(Z, M, O, true)

@@ -208,7 +208,7 @@ __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15)
 // orbitals of grids up to 8192 points fit the LDS.
 __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int ncol_max, int nent_max,
                                             int nmaxd, int nat_max, int ntask_max, int block,
-                                            int rho_lds, int mixt, int gcol = 0) {
+                                            int rho_lds, int mixt, int gcol = 0, int ptpl = 0) {
     const size_t c = fp64 ? 16 : 8;  // complex
     const size_t r = fp64 ? 8 : 4;   // real
     const int na = nat_max > 0 ? nat_max : 1;
@@ -229,7 +229,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
     L.wacc = o; o = al16(o + 8 * 4 * size_t(block / 64));  // FP64 current partial per wave
     L.nlm = o; o = al16(o + 8 * 20 * size_t(ntask_max > 0 ? ntask_max : 1));  // current moments per task
     // point-major projector tables staged in LDS (sl): 16-bit CSR, packed entries, radial factors
-    L.ptp = o; o = al16(o + (sl ? 2 * size_t(ng_max + 1) : 0));
+    L.ptp = o; o = al16(o + ((sl || ptpl) ? 2 * size_t(ng_max + 1) : 0));
     L.ptk = o; o = al16(o + (sl ? (fp64 ? 16 : 8) * size_t(nent_max) : 0));  // PtRec records
     L.rho = o; o = al16(o + (rho_lds ? 8 * size_t(ng_max) : 0));  // FP64 density partial
     L.tmix = o; o = al16(o + (mixt ? c * size_t(ng_max) : 0));      // mixed-derivative intermediate
@@ -239,7 +239,7 @@ __host__ __device__ inline PropLds prop_lds(int fp64, int sl, int ng_max, int nc
 
 inline size_t propagate_lds_bytes_inl(int fp64, int sl, const PropArgs &a, int block) {
     return prop_lds(fp64, sl, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd, a.nat_max, a.ntask_max,
-                    block, a.rho_lds, a.mixt, a.gcol != nullptr).total;
+                    block, a.rho_lds, a.mixt, a.gcol != nullptr, a.ptp_lds).total;
 }
 
 // Layout of one workgroup's global column tables (bytes, 256-aligned stride): geometry, phase
@@ -359,7 +359,9 @@ __device__ __forceinline__ void nl_current(const double *m, double Es, double Ep
 // formed while the projections run (before their barrier), and the pair (1,2) direct.
 // GC: the per-column-image tables in the work item's part of a.gcol (global memory, read and
 // written only by this workgroup, ordered by its barriers) instead of LDS.
-template <typename R, int ZL, int NONORTH, int MAXT, int MINW, bool SL, bool RAGGED, bool ITIME, bool GC = false>
+// SL: 1 the point-major projector records and their CSR pointers staged in LDS; 2 the CSR
+// pointers only (records read from global memory); 0 both from global memory.
+template <typename R, int ZL, int NONORTH, int MAXT, int MINW, int SL, bool RAGGED, bool ITIME, bool GC = false>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(MINW, 8)))
 void k_propagate(PropArgs a) {
     using C = typename CT<R>::T;
@@ -380,8 +382,9 @@ void k_propagate(PropArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int NW = BS >> 6;
 
-    const PropLds L = prop_lds(sizeof(R) == 8, SL, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd,
-                               a.nat_max, a.ntask_max, BS, a.rho_lds, NONORTH == 2, GC);
+    const PropLds L = prop_lds(sizeof(R) == 8, SL == 1, a.ng_max, a.ncol_max, a.nent_max, a.nmaxd,
+                               a.nat_max, a.ntask_max, BS, a.rho_lds, NONORTH == 2, GC, SL == 2);
+    constexpr bool ptpl = SL == 2;
     const PropGcol G = prop_gcol(sizeof(R) == 8, a.ncol_max);
     char *gcb = GC ? a.gcol + size_t(blockIdx.x) * G.stride : nullptr;
     C *W = reinterpret_cast<C *>(smem + L.W);
@@ -467,9 +470,11 @@ void k_propagate(PropArgs a) {
     for (int i = tid; i <= nat; i += BS) atk_l[i] = I.atom_task[i];
     for (int i = tid; i < ntask; i += BS) task_l[i] = gld(task + i);
 
-    if (SL) {
+    if (SL != 0) {
         const auto *p16 = gview(I.pt_ptr16);
         for (int i = tid; i <= ng; i += BS) ptp_l[i] = p16[i];
+    }
+    if (SL == 1) {
         for (int e = tid; e < I.nent; e += BS) {
             const uint32_t pk = pt_pack[e];  // column image | stored a_3 step << 16
             PtRec<R> rec;
@@ -864,7 +869,7 @@ void k_propagate(PropArgs a) {
                         h.y = fma(t2.x, s.y, h.y);
                         h.y = fma(-t2.y, s.x, h.y);
                     };
-                    if (SL) {  // LDS records; FP32 records hold the byte offset of the coefficients
+                    if (SL == 1) {  // LDS records; FP32 records hold the byte offset of the coefficients
                         const PtRec<R> *r1 = ptk_l + int(ptp_l[p + 1]);
                         for (const PtRec<R> *r = ptk_l + int(ptp_l[p]); r != r1; ++r) {
                             const PtRec<R> rec = *r;
@@ -873,11 +878,18 @@ void k_propagate(PropArgs a) {
                                 : AB[rec.pk & 0xffffu];
                             scatter_one(rec.pk, rec.g, q);
                         }
-                    } else {
-                        const int e1 = pt_ptr[p + 1];
-                        for (int e = pt_ptr[p]; e < e1; ++e) {
-                            const uint32_t pk = pt_pack[e];
-                            scatter_one(pk, pgt[e], AB[pk & 0xffffu]);
+                    } else {  // the same records in global memory, one load per entry
+                        const auto *recs = gview(reinterpret_cast<const PtRec<R> *>(I.pt_rec));
+                        const int e0 = ptpl ? int(ptp_l[p]) : pt_ptr[p];
+                        const int e1 = ptpl ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
+                        for (int e = e0; e < e1; ++e) {
+                            PtRec<R> rec;
+                            rec.pk = recs[e].pk;
+                            rec.g = recs[e].g;
+                            const Q4 q = (sizeof(R) == 4)
+                                ? *reinterpret_cast<const Q4 *>(reinterpret_cast<const char *>(AB) + (rec.pk & 0xffffu))
+                                : AB[rec.pk & 0xffffu];
+                            scatter_one(rec.pk, rec.g, q);
                         }
                     }
                     hz[z] = h;

@@ -88,6 +88,7 @@ struct TableSet {
     std::vector<float> chunk_gf;
     std::vector<int> atom_chunk;   // [nat+1] first chunk of each atom
     std::vector<uint16_t> pt_ptr16;
+    std::vector<uint32_t> pt_rec32, pt_rec64;  // interleaved entry records (words), FP32 / FP64
     std::vector<int2> task;
     std::vector<double> atom_tau, atom_par;
     int nat = 0;
@@ -102,6 +103,7 @@ struct TableSet {
     float *d_pt_gf = nullptr;
     int *d_pt_ptr = nullptr, *d_atom_task = nullptr;
     uint16_t *d_pt_ptr16 = nullptr;
+    uint32_t *d_pt_rec = nullptr;
     uint32_t *d_chunk_pack = nullptr;
     double *d_chunk_g = nullptr;
     float *d_chunk_gf = nullptr;
@@ -135,6 +137,7 @@ struct ShapeClass {
     bool nonorth;
     int zl = 0, block = 0, minw = 0, sl = 0, rho_lds = 0, ragged = 0, mixt = 0;
     int gc = 0;                 // FP64 column tables in global memory (grids beyond the LDS otherwise)
+    int ptpl = 0;               // no LDS records: the CSR pointers alone staged in LDS
     char *gcol = nullptr;       // their buffer, one slice of gstride bytes per work item of the class
     size_t gstride = 0;
     int wbeg = 0, wend = 0;
@@ -496,6 +499,24 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     if (T.pt_pack.size() > 65535) return fail(TDKS_E_UNSUPPORTED, "more than 65535 projector entries");
     T.pt_ptr16.assign(T.pt_ptr.begin(), T.pt_ptr.end());
     T.pt_gf.assign(T.pt_g.begin(), T.pt_g.end());
+    // records for the scatter from global memory: FP32 {byte offset of the column image's 16-byte
+    // coefficients | a_3 step << 16, g}; FP64 {column image | a_3 step << 16, 0, g}
+    T.pt_rec32.resize(2 * T.pt_pack.size());
+    T.pt_rec64.resize(4 * T.pt_pack.size());
+    for (size_t e = 0; e < T.pt_pack.size(); ++e) {
+        const uint32_t pk = T.pt_pack[e];
+        const float gf = float(T.pt_g[e]);
+        uint32_t gb;
+        std::memcpy(&gb, &gf, 4);
+        T.pt_rec32[2 * e] = ((pk & 0xffffu) * 16u) | (pk & 0xffff0000u);
+        T.pt_rec32[2 * e + 1] = gb;
+        uint64_t db;
+        std::memcpy(&db, &T.pt_g[e], 8);
+        T.pt_rec64[4 * e] = pk;
+        T.pt_rec64[4 * e + 1] = 0;
+        T.pt_rec64[4 * e + 2] = uint32_t(db & 0xffffffffu);
+        T.pt_rec64[4 * e + 3] = uint32_t(db >> 32);
+    }
     return TDKS_OK;
 }
 
@@ -624,6 +645,7 @@ PropArgs class_args(tdks_ctx *c, const ShapeClass &S, int mode, const double *A,
     a.rho_lds = S.rho_lds;
     a.mixt = S.mixt;
     a.gcol = S.gcol;
+    a.ptp_lds = S.ptpl;
     a.nat_max = S.nat_max;
     a.ntask_max = S.ntask_max;
     a.apply_in = nullptr;
@@ -1090,10 +1112,11 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
     }
     for (ShapeClass &S : c->classes) {
         PropArgs a = class_args(c, S, MODE_STEP, nullptr, nullptr);
-        auto fits = [&](int sl, int rho, int mixt, int gc = 0) {
+        auto fits = [&](int sl, int rho, int mixt, int gc = 0, int ptpl = 0) {
             a.rho_lds = rho;
             a.mixt = mixt;
             a.gcol = gc ? reinterpret_cast<char *>(256) : nullptr;  // only its presence counts here
+            a.ptp_lds = ptpl;
             return propagate_lds_bytes(c->fp64, sl, a, S.block) <= 160 * 1024;
         };
         // non-orthogonal cells: the mixed-derivative intermediate when it fits beside the
@@ -1109,9 +1132,13 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         // column tables go to a per-work-item global buffer
         S.gc = (c->fp64 && !fits(0, 0, S.mixt) && fits(0, 0, 0, 1)) ? 1 : 0;
         if (S.gc) S.mixt = 0;
+        // without LDS records the scatter reads its records from global memory: its CSR
+        // pointers (2 bytes per point) from LDS when they fit
+        S.ptpl = (!S.sl && fits(0, S.rho_lds, S.mixt, S.gc, 1)) ? 1 : 0;
         a.rho_lds = S.rho_lds;
         a.mixt = S.mixt;
         a.gcol = S.gc ? reinterpret_cast<char *>(256) : nullptr;
+        a.ptp_lds = S.ptpl;
         S.gstride = S.gc ? propagate_gcol_stride(c->fp64, S.ncol_max) : 0;
         const size_t lds = propagate_lds_bytes(c->fp64, S.sl, a, S.block);
         if (lds > 160 * 1024)
@@ -1219,6 +1246,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         CHK(upload(c, &T.d_col_j01, T.col_j01));
         CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
         CHK(upload(c, &T.d_pt_ptr16, T.pt_ptr16));
+        CHK(upload(c, &T.d_pt_rec, c->fp64 ? T.pt_rec64 : T.pt_rec32));
         CHK(upload(c, &T.d_pt_pack, T.pt_pack));
         CHK(upload(c, &T.d_pt_g, T.pt_g));
         CHK(upload(c, &T.d_pt_gf, T.pt_gf));
@@ -1313,6 +1341,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         D.col_j01 = T.d_col_j01;
         D.pt_ptr = T.d_pt_ptr;
         D.pt_ptr16 = T.d_pt_ptr16;
+        D.pt_rec = T.d_pt_rec;
         D.nent = int(T.pt_pack.size());
         D.pt_pack = T.d_pt_pack;
         D.pt_gf = T.d_pt_gf;
