@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="two-step sub-simulations (64 = full workload)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-others", action="store_true", help="leave out the HHG and uneven workloads")
     ap.add_argument("--skip-ground-state", action="store_true",
                     help="leave out the ground-state iteration measurement (keeps a profile of the "
                          "step kernel free of its launches)")
@@ -296,6 +297,27 @@ def main():
                  / HBM_PEAK_GBS}
         log(f"  plain FP64: {plain['value']:.3e} updates/s")
 
+    # ---- the other batched FP32 workloads: HHG two-step (64 x 64 k x 16 bands on 20^3, at the
+    # pulse peak) and the uneven 40-instance batch (four shape classes launched concurrently)
+    others = {}
+    if not args.skip_others:
+        import workloads as W
+        for key, name, start in (("hhg_two_step", "hhg_twostep_g20_mp4_s4", None), ("uneven", "uneven40", 0)):
+            wlo = W.config(name)
+            ins = wlo.instances
+            st = wlo.steps // 2 if start is None else start
+            Ao = wlo.field.table(K + Wm + 4, wlo.dt, start=st)
+            upd_o = sum(i.n_k * i.n_bands * i.ng for i in ins)
+            with tdks.Propagator(ins, precision="fp32", dt=wlo.dt) as p:
+                load_all(p, ins, 3000, torch)
+                elo = timed_steps(p, Ao, K, Wm, torch)
+                kto = p.time_kernels(Ao[K + Wm:K + Wm + 2])
+                tilo = p.tiling()
+            others[key] = {"workload": name, "value": upd_o * K / elo, "ms_per_step": 1e3 * elo / K,
+                           "propagate_ms_eager": kto["propagate_ms"], "updates_per_step": upd_o,
+                           "instances": len(ins), "tiling_first_class": tilo}
+            log(f"  {name} FP32: {others[key]['value']:.3e} updates/s, {others[key]['ms_per_step']:.2f} ms/step")
+
     out = {
         "metric": "k*band*gridpt*step updates/s (batched FP32 two-step)",
         "value": value,
@@ -322,6 +344,7 @@ def main():
         "fp32_vs_fp64_dJ_rel_err": acc,
         "ground_state": ground,
         "predictor_corrector": pc,
+        "other_workloads_fp32": others or None,
     }
     print(json.dumps(out))
 

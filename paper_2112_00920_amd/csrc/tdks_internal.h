@@ -44,9 +44,9 @@ struct DevInst {
     const uint32_t *pt_pack;   // [nent] packed entries
     const float *pt_gf;        // [nent] radial factors, FP32 copy
     const double *pt_gd;       // [nent] ... FP64 copy
-    const void *pt_rec;        // [nent] the same entries interleaved with their radial factors in the
-                               // propagation precision: FP32 {byte offset of the column image's
-                               // scatter coefficients | a_3 step << 16, g}, FP64 {pack, 0, g}
+    const void *pt_rec;        // [nent] FP32 only: the same entries interleaved with their radial
+                               // factors, {byte offset of the column image's scatter coefficients |
+                               // a_3 step << 16, g}
     // chunks: up to 4 consecutive support points of one column image (consecutive j2,
     // no periodic wrap inside), each packed as its first point's grid index p |
     // (j2 - r + N3 + 3) << 13 | col << 20; radial factors g of the 4 points, zero-padded

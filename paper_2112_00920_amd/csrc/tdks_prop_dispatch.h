@@ -39,11 +39,18 @@ static hipError_t launch_zl(const PropArgs &a, int n_items, int block, hipStream
 template <bool IT>
 static hipError_t dispatch(const PropArgs &a, int n_items, int block, int zl, int minw, int sl, int ragged,
                            hipStream_t s) {
+// FP64 reads the projector records from global memory only (SL 0); FP32 stages them (1) or
+// their CSR pointers (2) in LDS when they fit
 #define TDKS_CASE(Z, M, O, RG)                                                                      \
     if (ragged == RG && zl == Z && block <= M && minw == O) {                                       \
-        return sl ? launch_zl<Z, M, O, 1, RG>(a, n_items, block, s)                                 \
-                  : a.ptp_lds ? launch_zl<Z, M, O, 2, RG>(a, n_items, block, s)                     \
-                              : launch_zl<Z, M, O, 0, RG>(a, n_items, block, s);                    \
+        if constexpr (sizeof(REAL) == 8) {                                                          \
+            if (sl || a.ptp_lds) return hipErrorInvalidValue;                                       \
+            return launch_zl<Z, M, O, 0, RG>(a, n_items, block, s);                                 \
+        } else {                                                                                    \
+            return sl ? launch_zl<Z, M, O, 1, RG>(a, n_items, block, s)                             \
+                      : a.ptp_lds ? launch_zl<Z, M, O, 2, RG>(a, n_items, block, s)                 \
+                                  : launch_zl<Z, M, O, 0, RG>(a, n_items, block, s);                \
+        }                                                                                           \
     }
 #define TDKS_CASE_EVEN(Z, M, O) TDKS_CASE(Z, M, O, false)
 #define TDKS_CASE_RAGGED(Z, M, O) TDKS_CASE(Z, M, O, true)

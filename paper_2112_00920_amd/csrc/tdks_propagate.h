@@ -878,7 +878,7 @@ void k_propagate(PropArgs a) {
                                 : AB[rec.pk & 0xffffu];
                             scatter_one(rec.pk, rec.g, q);
                         }
-                    } else {  // the same records in global memory, one load per entry
+                    } else if (sizeof(R) == 4) {  // FP32: the same records in global memory, one load each
                         const auto *recs = gview(reinterpret_cast<const PtRec<R> *>(I.pt_rec));
                         const int e0 = ptpl ? int(ptp_l[p]) : pt_ptr[p];
                         const int e1 = ptpl ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
@@ -886,10 +886,14 @@ void k_propagate(PropArgs a) {
                             PtRec<R> rec;
                             rec.pk = recs[e].pk;
                             rec.g = recs[e].g;
-                            const Q4 q = (sizeof(R) == 4)
-                                ? *reinterpret_cast<const Q4 *>(reinterpret_cast<const char *>(AB) + (rec.pk & 0xffffu))
-                                : AB[rec.pk & 0xffffu];
+                            const Q4 q = *reinterpret_cast<const Q4 *>(reinterpret_cast<const char *>(AB) + (rec.pk & 0xffffu));
                             scatter_one(rec.pk, rec.g, q);
+                        }
+                    } else {  // FP64: packed entries and radial factors from their own arrays
+                        const int e1 = pt_ptr[p + 1];
+                        for (int e = pt_ptr[p]; e < e1; ++e) {
+                            const uint32_t pk = pt_pack[e];
+                            scatter_one(pk, pgt[e], AB[pk & 0xffffu]);
                         }
                     }
                     hz[z] = h;

@@ -88,7 +88,7 @@ struct TableSet {
     std::vector<float> chunk_gf;
     std::vector<int> atom_chunk;   // [nat+1] first chunk of each atom
     std::vector<uint16_t> pt_ptr16;
-    std::vector<uint32_t> pt_rec32, pt_rec64;  // interleaved entry records (words), FP32 / FP64
+    std::vector<uint32_t> pt_rec32;  // interleaved FP32 entry records (words)
     std::vector<int2> task;
     std::vector<double> atom_tau, atom_par;
     int nat = 0;
@@ -499,10 +499,9 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     if (T.pt_pack.size() > 65535) return fail(TDKS_E_UNSUPPORTED, "more than 65535 projector entries");
     T.pt_ptr16.assign(T.pt_ptr.begin(), T.pt_ptr.end());
     T.pt_gf.assign(T.pt_g.begin(), T.pt_g.end());
-    // records for the scatter from global memory: FP32 {byte offset of the column image's 16-byte
-    // coefficients | a_3 step << 16, g}; FP64 {column image | a_3 step << 16, 0, g}
+    // records for the FP32 scatter from global memory: {byte offset of the column image's 16-byte
+    // coefficients | a_3 step << 16, g}
     T.pt_rec32.resize(2 * T.pt_pack.size());
-    T.pt_rec64.resize(4 * T.pt_pack.size());
     for (size_t e = 0; e < T.pt_pack.size(); ++e) {
         const uint32_t pk = T.pt_pack[e];
         const float gf = float(T.pt_g[e]);
@@ -510,12 +509,6 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
         std::memcpy(&gb, &gf, 4);
         T.pt_rec32[2 * e] = ((pk & 0xffffu) * 16u) | (pk & 0xffff0000u);
         T.pt_rec32[2 * e + 1] = gb;
-        uint64_t db;
-        std::memcpy(&db, &T.pt_g[e], 8);
-        T.pt_rec64[4 * e] = pk;
-        T.pt_rec64[4 * e + 1] = 0;
-        T.pt_rec64[4 * e + 2] = uint32_t(db & 0xffffffffu);
-        T.pt_rec64[4 * e + 3] = uint32_t(db >> 32);
     }
     return TDKS_OK;
 }
@@ -1132,9 +1125,10 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         // column tables go to a per-work-item global buffer
         S.gc = (c->fp64 && !fits(0, 0, S.mixt) && fits(0, 0, 0, 1)) ? 1 : 0;
         if (S.gc) S.mixt = 0;
-        // without LDS records the scatter reads its records from global memory: its CSR
-        // pointers (2 bytes per point) from LDS when they fit
-        S.ptpl = (!S.sl && fits(0, S.rho_lds, S.mixt, S.gc, 1)) ? 1 : 0;
+        // without LDS records the FP32 scatter reads its records from global memory: its CSR
+        // pointers (2 bytes per point) from LDS when they fit (FP64 reads both from global
+        // memory: 5 % faster than its 16-byte records with the pointers in LDS)
+        S.ptpl = (!c->fp64 && !S.sl && fits(0, S.rho_lds, S.mixt, S.gc, 1)) ? 1 : 0;
         a.rho_lds = S.rho_lds;
         a.mixt = S.mixt;
         a.gcol = S.gc ? reinterpret_cast<char *>(256) : nullptr;
@@ -1246,7 +1240,7 @@ static int create_impl(const tdks_instance_desc *desc, int n_inst, const tdks_op
         CHK(upload(c, &T.d_col_j01, T.col_j01));
         CHK(upload(c, &T.d_pt_ptr, T.pt_ptr));
         CHK(upload(c, &T.d_pt_ptr16, T.pt_ptr16));
-        CHK(upload(c, &T.d_pt_rec, c->fp64 ? T.pt_rec64 : T.pt_rec32));
+        if (!c->fp64) CHK(upload(c, &T.d_pt_rec, T.pt_rec32));
         CHK(upload(c, &T.d_pt_pack, T.pt_pack));
         CHK(upload(c, &T.d_pt_g, T.pt_g));
         CHK(upload(c, &T.d_pt_gf, T.pt_gf));
