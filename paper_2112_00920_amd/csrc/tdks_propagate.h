@@ -412,6 +412,10 @@ void k_propagate(PropArgs a) {
     const Q4 *chunk_g = reinterpret_cast<const Q4 *>(chunktab<R>(I));
     const auto *pt_ptr = gview(I.pt_ptr);
     const auto *pt_pack = gview(I.pt_pack);
+    // FP32 scatter records in device memory (read here once: the instance table is global
+    // memory, which the kernel's stores could alias, so a read inside the loops is repeated)
+    const TDKS_GLOBAL PtRec<R> *pt_recs =
+        (SL != 1 && sizeof(R) == 4) ? gview(reinterpret_cast<const PtRec<R> *>(I.pt_rec)) : nullptr;
     const int2 *task = I.task;
     const auto *atom_task = gview(I.atom_task);
     const auto *kcart = gview(I.kcart);
@@ -879,7 +883,7 @@ void k_propagate(PropArgs a) {
                             scatter_one(rec.pk, rec.g, q);
                         }
                     } else if (sizeof(R) == 4) {  // FP32: the same records in global memory, one load each
-                        const auto *recs = gview(reinterpret_cast<const PtRec<R> *>(I.pt_rec));
+                        const auto *recs = pt_recs;
                         const int e0 = ptpl ? int(ptp_l[p]) : pt_ptr[p];
                         const int e1 = ptpl ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
                         for (int e = e0; e < e1; ++e) {
@@ -913,6 +917,17 @@ void k_propagate(PropArgs a) {
                     const int mo = HORNER ? norder + 1 - m : m;  // Horner runs the orders backwards
                     const double rm = (mo == 1) ? 1.0 : (mo == 2) ? 0.5 : (mo == 3) ? (1.0 / 3.0) : 0.25;
                     const R cm = R(a.dt * rm);
+                    // Horner: u of the owned points, requested together so that their latencies
+                    // overlap (one at a time, the loads wait for each other)
+                    C uh[HORNER ? ZL : 1];
+                    if (HORNER) {
+#pragma unroll
+                        for (int z = 0; z < (HORNER ? ZL : 0); ++z) {
+                            uh[z].x = R(0);
+                            uh[z].y = R(0);
+                            if (active && TDKS_ZOK(z)) uh[z] = gld(src + pw + plane * z);
+                        }
+                    }
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
                         C wn;  // (-i dt/m) h w, or (-tau/m) h w in imaginary time (dt holds tau)
@@ -924,10 +939,7 @@ void k_propagate(PropArgs a) {
                             wn.y = -cm * hz[z].x;
                         }
                         if (HORNER) {  // v <- u + wn, into W also after the last order
-                            C u0;
-                            u0.x = R(0);
-                            u0.y = R(0);
-                            if (active && TDKS_ZOK(z)) u0 = gld(src + pw + plane * z);
+                            const C u0 = uh[HORNER ? z : 0];
                             wn.x += u0.x;
                             wn.y += u0.y;
                             if (active && TDKS_ZOK(z)) W[pw + plane * z] = wn;
