@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--skip-ground-state", action="store_true",
                     help="leave out the ground-state iteration measurement (keeps a profile of the "
                          "step kernel free of its launches)")
+    ap.add_argument("--uneven-classes", action="store_true",
+                    help="also time each shape class of the uneven batch alone (one context per class)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB -> 1 GiB device copy kernel (torch neg), so that a counter "
                          "profile of this command holds a kernel of known HBM traffic")
@@ -317,6 +319,27 @@ def main():
                            "propagate_ms_eager": kto["propagate_ms"], "updates_per_step": upd_o,
                            "instances": len(ins), "tiling_first_class": tilo}
             log(f"  {name} FP32: {others[key]['value']:.3e} updates/s, {others[key]['ms_per_step']:.2f} ms/step")
+            if key == "uneven" and args.uneven_classes:
+                # each shape class (cell kind and grid) in a context of its own: its step alone
+                classes = {}
+                for idx, inst in enumerate(ins):
+                    classes.setdefault((inst.cell, tuple(inst.grid)), []).append(idx)
+                alone = {}
+                for (cell, grid), idxs in classes.items():
+                    sub = [ins[i] for i in idxs]
+                    upd_c = sum(i.n_k * i.n_bands * i.ng for i in sub)
+                    with tdks.Propagator(sub, precision="fp32", dt=wlo.dt) as p:
+                        load_all(p, sub, 3000, torch)
+                        elc = timed_steps(p, Ao, K, Wm, torch)
+                        ktc = p.time_kernels(Ao[K + Wm:K + Wm + 2])
+                        tilc = p.tiling()
+                    label = f"{cell} {grid[0]}x{grid[1]}x{grid[2]}"
+                    alone[label] = {"instances": len(sub), "updates_per_step": upd_c,
+                                    "ms_per_step": 1e3 * elc / K, "propagate_ms_eager": ktc["propagate_ms"],
+                                    "value": upd_c * K / elc, "tiling": tilc}
+                    log(f"    class {label} alone ({len(sub)} instances): {1e3 * elc / K:.3f} ms/step, "
+                        f"{upd_c * K / elc:.3e} updates/s, tiling {tilc}")
+                others[key]["classes_alone"] = alone
 
     out = {
         "metric": "k*band*gridpt*step updates/s (batched FP32 two-step)",
