@@ -513,19 +513,51 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
     return TDKS_OK;
 }
 
-// projection tasks: contiguous chunk ranges of one atom, sized so that the block's waves
-// get about one task each (one wave reduction per task)
+// projection tasks: contiguous chunk ranges of one atom (one wave reduction each), taken by the
+// block's waves in turn (task t by wave t mod NW). The split minimises the busiest wave's work,
+// counted as 64-chunk passes plus 0.4 of a pass for each task's reduction, over two families:
+// every atom cut into m equal ranges, and ranges of 64 j chunks; ties go to fewer tasks (LDS).
+// E.g. 8 atoms on 13 waves (20^3, 832 threads): two tasks per atom left three waves with two
+// tasks each, twice the others' work.
+std::vector<int2> split_tasks(const std::vector<int> &atom_chunk, int nat, int nwaves, int len_mode, int arg) {
+    std::vector<int2> task;
+    for (int a = 0; a < nat; ++a) {
+        const int b0 = atom_chunk[a], cnt = atom_chunk[a + 1] - b0;
+        if (cnt <= 0) continue;
+        const int len = len_mode ? 64 * arg : (cnt + arg - 1) / arg;
+        for (int s = 0; s < cnt; s += len) task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
+    }
+    (void)nwaves;
+    return task;
+}
+
+double tasks_cost(const std::vector<int2> &task, int nwaves) {
+    std::vector<double> w(nwaves, 0.0);
+    for (size_t t = 0; t < task.size(); ++t) w[t % nwaves] += double(((task[t].y >> 8) + 63) / 64) + 0.4;
+    return *std::max_element(w.begin(), w.end());
+}
+
 void build_tasks(TableSet &T, int block) {
     const int nwaves = std::max(1, block / 64);
-    const long long total = std::max(1, T.atom_chunk[T.nat]);
-    T.task.clear();
+    const int max_tasks = std::max(4 * nwaves, T.nat);
+    std::vector<int2> best;
+    double best_cost = 0.0;
+    for (int mode = 0; mode < 2; ++mode)
+        for (int arg = 1; arg <= 32; ++arg) {
+            std::vector<int2> cand = split_tasks(T.atom_chunk, T.nat, nwaves, mode, arg);
+            if (cand.empty() || (int(cand.size()) > max_tasks && !best.empty())) continue;
+            const double c = tasks_cost(cand, nwaves);
+            if (best.empty() || c < best_cost - 1e-9 || (c < best_cost + 1e-9 && cand.size() < best.size())) {
+                best = std::move(cand);
+                best_cost = c;
+            }
+        }
+    T.task = best;
     T.atom_task.assign(T.nat + 1, 0);
+    size_t t = 0;
     for (int a = 0; a < T.nat; ++a) {
-        T.atom_task[a] = int(T.task.size());
-        const int b0 = T.atom_chunk[a], cnt = T.atom_chunk[a + 1] - b0;
-        const int nt = std::max(1, int((nwaves * (long long)cnt + total / 2) / total));
-        const int len = (cnt + nt - 1) / nt;
-        for (int s = 0; s < cnt; s += len) T.task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
+        T.atom_task[a] = int(t);
+        while (t < T.task.size() && (T.task[t].y & 255) == a) ++t;
     }
     T.atom_task[T.nat] = int(T.task.size());
 }
