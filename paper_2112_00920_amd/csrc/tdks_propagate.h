@@ -696,18 +696,36 @@ void k_propagate(PropArgs a) {
                         part[4 * t + l] = v;
                     }
                 }
+                // pair (1, 2) of the mixed derivatives at the owned points, cx2 D1_2 D1_1 w, formed
+                // here from D1_1 w on the segment and two points beyond each end (periodic along
+                // a_3) and kept until the stencil: 4 reads per point instead of 16
+                C m12[NONORTH == 2 ? ZL : 1];
                 if (NONORTH == 2 && active) {
                     // mixed-derivative intermediate of the owned points, T = cx0 D1_1 w + cx1 D1_2 w
                     const int pt = opq(pbase);
                     int oyt[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) oyt[q] = opq(oy[q]);
+                    C gyh[ZL + 4];  // D1_1 w at z0 - 2 + j
+#pragma unroll
+                    for (int j = 0; j < ZL + 4; ++j) {
+                        gyh[j].x = R(0);
+                        gyh[j].y = R(0);
+                        if (!TDKS_ZOK(j - 4)) continue;
+                        int zw = z0 + j - 2;
+                        zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
+                        const int p = pt + plane * zw;
+                        const C y1 = W[p + oyt[0]], y2 = W[p + oyt[1]], y3 = W[p + oyt[2]], y4 = W[p + oyt[3]];
+                        gyh[j].x = R(D1C1) * (y1.x - y2.x) + R(D1C2) * (y3.x - y4.x);
+                        gyh[j].y = R(D1C1) * (y1.y - y2.y) + R(D1C2) * (y3.y - y4.y);
+                    }
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
+                        m12[NONORTH == 2 ? z : 0].x = R(0);
+                        m12[NONORTH == 2 ? z : 0].y = R(0);
                         if (!TDKS_ZOK(z)) continue;
                         const int zg = z0 + z;
                         const int p = pt + plane * zg;
-                        const C y1 = W[p + oyt[0]], y2 = W[p + oyt[1]], y3 = W[p + oyt[2]], y4 = W[p + oyt[3]];
                         C zn[4];  // +1, -1, +2, -2 along a_3 (periodic)
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
@@ -716,15 +734,19 @@ void k_propagate(PropArgs a) {
                             zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
                             zn[q] = W[pt + plane * zw];
                         }
-                        C gy, gz;  // D1_1 w, D1_2 w
-                        gy.x = R(D1C1) * (y1.x - y2.x) + R(D1C2) * (y3.x - y4.x);
-                        gy.y = R(D1C1) * (y1.y - y2.y) + R(D1C2) * (y3.y - y4.y);
+                        const C gy = gyh[z + 2];  // D1_1 w
+                        C gz;                     // D1_2 w
                         gz.x = R(D1C1) * (zn[0].x - zn[1].x) + R(D1C2) * (zn[2].x - zn[3].x);
                         gz.y = R(D1C1) * (zn[0].y - zn[1].y) + R(D1C2) * (zn[2].y - zn[3].y);
                         C tv;
                         tv.x = cx[0] * gy.x + cx[1] * gz.x;
                         tv.y = cx[0] * gy.y + cx[1] * gz.y;
                         TM[p] = tv;
+                        const C a1p = gyh[z + 3], a1m = gyh[z + 1], a2p = gyh[z + 4], a2m = gyh[z];
+                        C mv;
+                        mv.x = cx[2] * (R(D1C1) * (a1p.x - a1m.x) + R(D1C2) * (a2p.x - a2m.x));
+                        mv.y = cx[2] * (R(D1C1) * (a1p.y - a1m.y) + R(D1C2) * (a2p.y - a2m.y));
+                        m12[NONORTH == 2 ? z : 0] = mv;
                     }
                 }
                 __syncthreads();
@@ -818,15 +840,16 @@ void k_propagate(PropArgs a) {
                         h.y = fma(-b2[d], p2.x - m2.x, h.y);
                     }
                     if (NONORTH == 2) {
-                        // pairs (0, 1) and (0, 2): D1_0 T
+                        // pairs (0, 1) and (0, 2): D1_0 T; pair (1, 2) from the projection phase
                         const C tp1 = TM[p + oxl[0]], tm1 = TM[p + oxl[1]];
                         const C tp2 = TM[p + oxl[2]], tm2 = TM[p + oxl[3]];
                         h.x += R(D1C1) * (tp1.x - tm1.x) + R(D1C2) * (tp2.x - tm2.x);
                         h.y += R(D1C1) * (tp1.y - tm1.y) + R(D1C2) * (tp2.y - tm2.y);
+                        h.x += m12[NONORTH == 2 ? z : 0].x;
+                        h.y += m12[NONORTH == 2 ? z : 0].y;
                     }
-                    if (NONORTH) {
-                        // - sum_{d<e} g_de D1_d D1_e w, all from LDS (the pair (1, 2) only when the
-                        // others came through T)
+                    if (NONORTH == 1) {
+                        // - sum_{d<e} g_de D1_d D1_e w, all from LDS
                         int oz[4];
 #pragma unroll
                         for (int s = 0; s < 4; ++s) {
@@ -836,7 +859,7 @@ void k_propagate(PropArgs a) {
                             oz[s] = plane * (zw - zg);
                         }
 #pragma unroll
-                        for (int q = (NONORTH == 2 ? 2 : 0); q < 3; ++q) {
+                        for (int q = 0; q < 3; ++q) {
                             if (cx[q] == R(0)) continue;
                             C tot;
                             tot.x = R(0);
