@@ -934,7 +934,11 @@ void k_propagate(PropArgs a) {
                         for (int z = 0; z < ZL; ++z)
                             if (TDKS_ZOK(z)) gst(out + pw + plane * z, hz[z]);
                     }
-                } else {
+                }
+                if (!HORNER || a.mode != MODE_APPLY) {
+                    // the Taylor update; the register-sum form runs it in MODE_APPLY too (one
+                    // order: the sum is discarded, nothing is written to W), which spares the
+                    // step's loop a merge of the sums at every order
                     // dt/m through a reciprocal of the (wave-uniform) order: one multiply
                     // instead of a double-precision division per thread
                     const int mo = HORNER ? norder + 1 - m : m;  // Horner runs the orders backwards
