@@ -814,10 +814,18 @@ void k_propagate(PropArgs a) {
                         zn[s] = W[pb + plane * zw];
                     }
                     const C cen = W[p];
-                    const R cv = c0 + (VREG ? vz[VREG ? z : 0] : vtot[p]);
+                    // a potential read from memory (long FP32 segments) enters after the
+                    // kinetic sums, so that the arithmetic before it covers the load's latency
+                    const R vmem = VREG ? R(0) : vtot[p];
                     C h;
-                    h.x = cv * cen.x;
-                    h.y = cv * cen.y;
+                    if (VREG) {
+                        const R cv = c0 + vz[VREG ? z : 0];
+                        h.x = cv * cen.x;
+                        h.y = cv * cen.y;
+                    } else {
+                        h.x = R(0);
+                        h.y = R(0);
+                    }
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         C p1, m1, p2, m2;
@@ -838,6 +846,11 @@ void k_propagate(PropArgs a) {
                         h.y = fma(a2[d], p2.y + m2.y, h.y);
                         h.y = fma(-b1[d], p1.x - m1.x, h.y);
                         h.y = fma(-b2[d], p2.x - m2.x, h.y);
+                    }
+                    if (!VREG) {
+                        const R cv = c0 + vmem;
+                        h.x = fma(cv, cen.x, h.x);
+                        h.y = fma(cv, cen.y, h.y);
                     }
                     if (NONORTH == 2) {
                         // pairs (0, 1) and (0, 2): D1_0 T; pair (1, 2) from the projection phase

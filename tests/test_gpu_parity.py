@@ -67,8 +67,20 @@ def test_apply_h(tdks, name, precision):
         np.testing.assert_allclose(prop.vloc(0), sysm.v_loc, rtol=0, atol=1e-13)
     want = np.stack([sysm.apply_h(sysm.k_cart[k] + A, 0.0, w[k]) for k in range(sysm.nk)])
     err = np.max(np.abs(got - want)) / np.max(np.abs(want))
-    _say(f"  rel err {err:.2e}")
-    assert err < (1e-13 if precision == "fp64" else 2e-6)
+    if precision == "fp64":
+        _say(f"  rel err {err:.2e}")
+        assert err < 1e-13
+        return
+    # FP32 bar from the arithmetic: the FP32 path rounds w to FP32 and sums the stencil,
+    # potential and projector terms in FP32. Rounding the input alone changes the FP64
+    # result by s_in (computed here with the oracle); the sums' own roundings are of the same
+    # order, since the terms exceed the result by the same kinetic conditioning, which grows
+    # as 1/h^2 with the grid. Bar: 10 s_in.
+    w32 = w.astype(np.complex64).astype(np.complex128)
+    want32 = np.stack([sysm.apply_h(sysm.k_cart[k] + A, 0.0, w32[k]) for k in range(sysm.nk)])
+    s_in = np.max(np.abs(want32 - want)) / np.max(np.abs(want))
+    _say(f"  rel err {err:.2e}; input rounding alone {s_in:.2e} (bar 10x)")
+    assert err < 10 * s_in
 
 
 def run_gpu(tdks, insts, u0s, A, precision="fp64", hxc="scf", frozen=None, k_fracs=None, **kw):
