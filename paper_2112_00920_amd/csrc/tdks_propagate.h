@@ -707,15 +707,18 @@ void k_propagate(PropArgs a) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) oyt[q] = opq(oy[q]);
                     C gyh[ZL + 4];  // D1_1 w at z0 - 2 + j
+                    C wcol[ZL + 4];  // w itself there, for D1_2 w at the owned points
 #pragma unroll
                     for (int j = 0; j < ZL + 4; ++j) {
                         gyh[j].x = R(0);
                         gyh[j].y = R(0);
+                        wcol[j] = gyh[j];
                         if (!TDKS_ZOK(j - 4)) continue;
                         int zw = z0 + j - 2;
                         zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
                         const int p = pt + plane * zw;
                         const C y1 = W[p + oyt[0]], y2 = W[p + oyt[1]], y3 = W[p + oyt[2]], y4 = W[p + oyt[3]];
+                        wcol[j] = W[p];
                         gyh[j].x = R(D1C1) * (y1.x - y2.x) + R(D1C2) * (y3.x - y4.x);
                         gyh[j].y = R(D1C1) * (y1.y - y2.y) + R(D1C2) * (y3.y - y4.y);
                     }
@@ -726,18 +729,11 @@ void k_propagate(PropArgs a) {
                         if (!TDKS_ZOK(z)) continue;
                         const int zg = z0 + z;
                         const int p = pt + plane * zg;
-                        C zn[4];  // +1, -1, +2, -2 along a_3 (periodic)
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const int dz = (q == 0) ? 1 : (q == 1) ? -1 : (q == 2) ? 2 : -2;
-                            int zw = zg + dz;
-                            zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
-                            zn[q] = W[pt + plane * zw];
-                        }
                         const C gy = gyh[z + 2];  // D1_1 w
+                        const C z1p = wcol[z + 3], z1m = wcol[z + 1], z2p = wcol[z + 4], z2m = wcol[z];
                         C gz;                     // D1_2 w
-                        gz.x = R(D1C1) * (zn[0].x - zn[1].x) + R(D1C2) * (zn[2].x - zn[3].x);
-                        gz.y = R(D1C1) * (zn[0].y - zn[1].y) + R(D1C2) * (zn[2].y - zn[3].y);
+                        gz.x = R(D1C1) * (z1p.x - z1m.x) + R(D1C2) * (z2p.x - z2m.x);
+                        gz.y = R(D1C1) * (z1p.y - z1m.y) + R(D1C2) * (z2p.y - z2m.y);
                         C tv;
                         tv.x = cx[0] * gy.x + cx[1] * gz.x;
                         tv.y = cx[0] * gy.y + cx[1] * gz.y;
