@@ -782,13 +782,15 @@ void k_propagate(PropArgs a) {
                 __syncthreads();
                 // ---- 2. h w along the owned column segment
                 // (opaque copies keep the compiler from hoisting every neighbour address
-                // out of the band and Taylor loops, which would pin them in registers)
+                // out of the band and Taylor loops, which would pin them in registers; the
+                // orthogonal kernels, with fewer neighbours, run faster with the in-plane
+                // offsets hoisted: 16^3 step launch -1.1 %, 20^3 -1.3 %)
                 const int pb = opq(pbase);
                 int oxl[4], oyl[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    oxl[s] = opq(ox[s]);
-                    oyl[s] = opq(oy[s]);
+                    oxl[s] = NONORTH ? opq(ox[s]) : ox[s];
+                    oyl[s] = NONORTH ? opq(oy[s]) : oy[s];
                 }
                 C hz[ZL];
 #pragma unroll
