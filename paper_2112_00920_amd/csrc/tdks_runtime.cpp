@@ -519,7 +519,8 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
 // every atom cut into m equal ranges, and ranges of 64 j chunks; ties go to fewer tasks (LDS).
 // E.g. 8 atoms on 13 waves (20^3, 832 threads): two tasks per atom left three waves with two
 // tasks each, twice the others' work.
-std::vector<int2> split_tasks(const std::vector<int> &atom_chunk, int nat, int nwaves, int len_mode, int arg) {
+// len_mode 0: every atom cut into arg equal ranges; 1: ranges of 64 arg chunks
+std::vector<int2> split_tasks(const std::vector<int> &atom_chunk, int nat, int len_mode, int arg) {
     std::vector<int2> task;
     for (int a = 0; a < nat; ++a) {
         const int b0 = atom_chunk[a], cnt = atom_chunk[a + 1] - b0;
@@ -527,7 +528,6 @@ std::vector<int2> split_tasks(const std::vector<int> &atom_chunk, int nat, int n
         const int len = len_mode ? 64 * arg : (cnt + arg - 1) / arg;
         for (int s = 0; s < cnt; s += len) task.push_back(make_int2(b0 + s, a | (std::min(len, cnt - s) << 8)));
     }
-    (void)nwaves;
     return task;
 }
 
@@ -544,7 +544,7 @@ void build_tasks(TableSet &T, int block) {
     double best_cost = 0.0;
     for (int mode = 0; mode < 2; ++mode)
         for (int arg = 1; arg <= 32; ++arg) {
-            std::vector<int2> cand = split_tasks(T.atom_chunk, T.nat, nwaves, mode, arg);
+            std::vector<int2> cand = split_tasks(T.atom_chunk, T.nat, mode, arg);
             if (cand.empty() || (int(cand.size()) > max_tasks && !best.empty())) continue;
             const double c = tasks_cost(cand, nwaves);
             if (best.empty() || c < best_cost - 1e-9 || (c < best_cost + 1e-9 && cand.size() < best.size())) {
