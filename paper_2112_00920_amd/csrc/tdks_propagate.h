@@ -696,10 +696,13 @@ void k_propagate(PropArgs a) {
                         part[4 * t + l] = v;
                     }
                 }
-                // pair (1, 2) of the mixed derivatives at the owned points, cx2 D1_2 D1_1 w, formed
-                // here from D1_1 w on the segment and two points beyond each end (periodic along
-                // a_3) and kept until the stencil: 4 reads per point instead of 16
-                C m12[NONORTH == 2 ? ZL : 1];
+                // Non-orthogonal cells: everything of h w at the owned points that needs no
+                // in-plane a_1 neighbour is formed here, from the column w(z0 - 2 .. z0 + ZL + 1)
+                // and its D1_1 w, which this phase reads anyway for the intermediate T: the a_2
+                // and a_3 parts of the stencil, the mixed pair (1, 2) = cx2 D1_2 D1_1 w, and the
+                // potential when it sits in registers. The sum is kept in registers until the
+                // stencil, which then adds only the a_1 part, D1_0 T and the non-local term.
+                C hpre[NONORTH == 2 ? ZL : 1];
                 if (NONORTH == 2 && active) {
                     // mixed-derivative intermediate of the owned points, T = cx0 D1_1 w + cx1 D1_2 w
                     const int pt = opq(pbase);
@@ -707,25 +710,44 @@ void k_propagate(PropArgs a) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) oyt[q] = opq(oy[q]);
                     C gyh[ZL + 4];  // D1_1 w at z0 - 2 + j
-                    C wcol[ZL + 4];  // w itself there, for D1_2 w at the owned points
+                    C wcol[ZL + 4];  // w itself there
+                    C hy[ZL];        // a_2 part of the stencil at the owned points
 #pragma unroll
                     for (int j = 0; j < ZL + 4; ++j) {
                         gyh[j].x = R(0);
                         gyh[j].y = R(0);
                         wcol[j] = gyh[j];
+                        if (j >= 2 && j < ZL + 2) hy[j - 2] = gyh[j];
                         if (!TDKS_ZOK(j - 4)) continue;
                         int zw = z0 + j - 2;
                         zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
                         const int p = pt + plane * zw;
                         const C y1 = W[p + oyt[0]], y2 = W[p + oyt[1]], y3 = W[p + oyt[2]], y4 = W[p + oyt[3]];
                         wcol[j] = W[p];
-                        gyh[j].x = R(D1C1) * (y1.x - y2.x) + R(D1C2) * (y3.x - y4.x);
-                        gyh[j].y = R(D1C1) * (y1.y - y2.y) + R(D1C2) * (y3.y - y4.y);
+                        C d1, d2;
+                        d1.x = y1.x - y2.x;
+                        d1.y = y1.y - y2.y;
+                        d2.x = y3.x - y4.x;
+                        d2.y = y3.y - y4.y;
+                        gyh[j].x = R(D1C1) * d1.x + R(D1C2) * d2.x;
+                        gyh[j].y = R(D1C1) * d1.y + R(D1C2) * d2.y;
+                        if (j >= 2 && j < ZL + 2) {
+                            C e;
+                            e.x = fma(a1[1], y1.x + y2.x, R(0));
+                            e.x = fma(a2[1], y3.x + y4.x, e.x);
+                            e.x = fma(b1[1], d1.y, e.x);
+                            e.x = fma(b2[1], d2.y, e.x);
+                            e.y = fma(a1[1], y1.y + y2.y, R(0));
+                            e.y = fma(a2[1], y3.y + y4.y, e.y);
+                            e.y = fma(-b1[1], d1.x, e.y);
+                            e.y = fma(-b2[1], d2.x, e.y);
+                            hy[j - 2] = e;
+                        }
                     }
 #pragma unroll
                     for (int z = 0; z < ZL; ++z) {
-                        m12[NONORTH == 2 ? z : 0].x = R(0);
-                        m12[NONORTH == 2 ? z : 0].y = R(0);
+                        hpre[NONORTH == 2 ? z : 0].x = R(0);
+                        hpre[NONORTH == 2 ? z : 0].y = R(0);
                         if (!TDKS_ZOK(z)) continue;
                         const int zg = z0 + z;
                         const int p = pt + plane * zg;
@@ -738,11 +760,31 @@ void k_propagate(PropArgs a) {
                         tv.x = cx[0] * gy.x + cx[1] * gz.x;
                         tv.y = cx[0] * gy.y + cx[1] * gz.y;
                         TM[p] = tv;
+                        // h so far: potential (from registers), a_2 and a_3 parts, pair (1, 2)
+                        C hv;
+                        if (VREG) {
+                            const R cv = c0 + vz[VREG ? z : 0];
+                            const C cen = wcol[z + 2];
+                            hv.x = cv * cen.x;
+                            hv.y = cv * cen.y;
+                        } else {
+                            hv.x = R(0);
+                            hv.y = R(0);
+                        }
+                        hv.x += hy[z].x;
+                        hv.y += hy[z].y;
+                        hv.x = fma(a1[2], z1p.x + z1m.x, hv.x);
+                        hv.x = fma(a2[2], z2p.x + z2m.x, hv.x);
+                        hv.x = fma(b1[2], z1p.y - z1m.y, hv.x);
+                        hv.x = fma(b2[2], z2p.y - z2m.y, hv.x);
+                        hv.y = fma(a1[2], z1p.y + z1m.y, hv.y);
+                        hv.y = fma(a2[2], z2p.y + z2m.y, hv.y);
+                        hv.y = fma(-b1[2], z1p.x - z1m.x, hv.y);
+                        hv.y = fma(-b2[2], z2p.x - z2m.x, hv.y);
                         const C a1p = gyh[z + 3], a1m = gyh[z + 1], a2p = gyh[z + 4], a2m = gyh[z];
-                        C mv;
-                        mv.x = cx[2] * (R(D1C1) * (a1p.x - a1m.x) + R(D1C2) * (a2p.x - a2m.x));
-                        mv.y = cx[2] * (R(D1C1) * (a1p.y - a1m.y) + R(D1C2) * (a2p.y - a2m.y));
-                        m12[NONORTH == 2 ? z : 0] = mv;
+                        hv.x += cx[2] * (R(D1C1) * (a1p.x - a1m.x) + R(D1C2) * (a2p.x - a2m.x));
+                        hv.y += cx[2] * (R(D1C1) * (a1p.y - a1m.y) + R(D1C2) * (a2p.y - a2m.y));
+                        hpre[NONORTH == 2 ? z : 0] = hv;
                     }
                 }
                 __syncthreads();
@@ -806,17 +848,25 @@ void k_propagate(PropArgs a) {
                     C zn[4];  // +1, -1, +2, -2
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
+                        zn[s].x = R(0);
+                        zn[s].y = R(0);
+                        if (NONORTH == 2) continue;  // the a_3 part came with hpre
                         const int dz = (s == 0) ? 1 : (s == 1) ? -1 : (s == 2) ? 2 : -2;
                         int zw = zg + dz;
                         zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
                         zn[s] = W[pb + plane * zw];
                     }
-                    const C cen = W[p];
+                    C cen;
+                    cen.x = R(0);
+                    cen.y = R(0);
+                    if (NONORTH != 2 || !VREG) cen = W[p];
                     // a potential read from memory (long FP32 segments) enters after the
                     // kinetic sums, so that the arithmetic before it covers the load's latency
                     const R vmem = VREG ? R(0) : vtot[p];
                     C h;
-                    if (VREG) {
+                    if (NONORTH == 2) {
+                        h = hpre[NONORTH == 2 ? z : 0];
+                    } else if (VREG) {
                         const R cv = c0 + vz[VREG ? z : 0];
                         h.x = cv * cen.x;
                         h.y = cv * cen.y;
@@ -825,7 +875,7 @@ void k_propagate(PropArgs a) {
                         h.y = R(0);
                     }
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
+                    for (int d = 0; d < (NONORTH == 2 ? 1 : 3); ++d) {
                         C p1, m1, p2, m2;
                         if (d == 0) {
                             p1 = W[p + oxl[0]]; m1 = W[p + oxl[1]]; p2 = W[p + oxl[2]]; m2 = W[p + oxl[3]];
@@ -851,13 +901,11 @@ void k_propagate(PropArgs a) {
                         h.y = fma(cv, cen.y, h.y);
                     }
                     if (NONORTH == 2) {
-                        // pairs (0, 1) and (0, 2): D1_0 T; pair (1, 2) from the projection phase
+                        // pairs (0, 1) and (0, 2): D1_0 T (the pair (1, 2) came with hpre)
                         const C tp1 = TM[p + oxl[0]], tm1 = TM[p + oxl[1]];
                         const C tp2 = TM[p + oxl[2]], tm2 = TM[p + oxl[3]];
                         h.x += R(D1C1) * (tp1.x - tm1.x) + R(D1C2) * (tp2.x - tm2.x);
                         h.y += R(D1C1) * (tp1.y - tm1.y) + R(D1C2) * (tp2.y - tm2.y);
-                        h.x += m12[NONORTH == 2 ? z : 0].x;
-                        h.y += m12[NONORTH == 2 ? z : 0].y;
                     }
                     if (NONORTH == 1) {
                         // - sum_{d<e} g_de D1_d D1_e w, all from LDS
