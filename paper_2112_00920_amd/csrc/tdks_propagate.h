@@ -835,6 +835,25 @@ void k_propagate(PropArgs a) {
                     oyl[s] = NONORTH ? opq(oy[s]) : oy[s];
                 }
                 C hz[ZL];
+                // long segments of orthogonal cells walk the column with a window of five
+                // values (z - 2 .. z + 2) in registers, one LDS read per point for the centre and
+                // the a_3 neighbours; short segments read them like the in-plane ones (a register
+                // copy measured no faster there), and a copy of a whole long segment spilled
+                constexpr bool WIN = !VREG && NONORTH == 0;
+                C win[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    win[q].x = R(0);
+                    win[q].y = R(0);
+                }
+                if (WIN && active) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        int zw = z0 - 2 + q;
+                        zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
+                        win[q] = W[pb + plane * zw];
+                    }
+                }
 #pragma unroll
                 for (int z = 0; z < ZL; ++z) {
                     hz[z].x = R(0);
@@ -842,15 +861,21 @@ void k_propagate(PropArgs a) {
                     if (!active || !TDKS_ZOK(z)) continue;
                     const int zg = z0 + z;
                     const int p = pb + plane * zg;
-                    // z neighbours from LDS like the in-plane ones (periodic wrap): a register
-                    // copy of the segment measured no faster for 4-point segments, and longer
-                    // ones spilled it (20^3 FP32 and 16^3 FP64 ran 14 % and 7 % slower)
+                    if (WIN) {  // a ring: position zg + d sits in win[(z + d + 2) % 5]
+                        int zw = zg + 2;
+                        zw = zw >= N2 ? zw - N2 : zw;
+                        win[(z + 4) % 5] = W[pb + plane * zw];
+                    }
                     C zn[4];  // +1, -1, +2, -2
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
                         zn[s].x = R(0);
                         zn[s].y = R(0);
                         if (NONORTH == 2) continue;  // the a_3 part came with hpre
+                        if (WIN) {
+                            zn[s] = win[(z + ((s == 0) ? 3 : (s == 1) ? 1 : (s == 2) ? 4 : 0)) % 5];
+                            continue;
+                        }
                         const int dz = (s == 0) ? 1 : (s == 1) ? -1 : (s == 2) ? 2 : -2;
                         int zw = zg + dz;
                         zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
@@ -859,7 +884,8 @@ void k_propagate(PropArgs a) {
                     C cen;
                     cen.x = R(0);
                     cen.y = R(0);
-                    if (NONORTH != 2 || !VREG) cen = W[p];
+                    if (WIN) cen = win[(z + 2) % 5];
+                    else if (NONORTH != 2 || !VREG) cen = W[p];
                     // a potential read from memory (long FP32 segments) enters after the
                     // kinetic sums, so that the arithmetic before it covers the load's latency
                     const R vmem = VREG ? R(0) : vtot[p];
