@@ -835,11 +835,12 @@ void k_propagate(PropArgs a) {
                     oyl[s] = NONORTH ? opq(oy[s]) : oy[s];
                 }
                 C hz[ZL];
-                // long segments of orthogonal cells walk the column with a window of five
-                // values (z - 2 .. z + 2) in registers, one LDS read per point for the centre and
-                // the a_3 neighbours; short segments read them like the in-plane ones (a register
-                // copy measured no faster there), and a copy of a whole long segment spilled
-                constexpr bool WIN = !VREG && NONORTH == 0;
+                // long FP32 segments and the FP64 kernels of orthogonal cells walk the column
+                // with a window of five values (z - 2 .. z + 2) in registers, one LDS read per
+                // point for the centre and the a_3 neighbours (20^3 FP32: spills 18 -> 9, step
+                // -3.8 %; FP64 -0.4 %); the 4-point FP32 segments read them like the in-plane ones
+                // (with the window: 0.6 % slower), and a copy of a whole long segment spilled
+                constexpr bool WIN = NONORTH == 0 && (!VREG || sizeof(R) == 8);
                 C win[5];
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
