@@ -1114,7 +1114,11 @@ void k_propagate(PropArgs a) {
                     if (!TDKS_ZOK(z)) continue;
                     const int zg = z0 + z;
                     const int p = pk0 + plane * zg;
-                    const C u = W[p];
+                    // FP64: the register sums still hold this thread's new values, and the centre
+                    // and the a_3 neighbours inside the segment come from them, the rest from LDS
+                    // (two-step FP64 -0.5 %; the FP32 16^3 kernel ran 0.7 % slower with it)
+                    constexpr bool ACCU = !HORNER && sizeof(R) == 8;
+                    const C u = ACCU ? acc[ACCU ? z : 0] : W[p];
                     qn[3] += u.x * u.x + u.y * u.y;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
@@ -1128,8 +1132,13 @@ void k_propagate(PropArgs a) {
                         } else {
 #pragma unroll
                             for (int s = 1; s <= 2; ++s) {
-                                const int zw = (zg + s >= N2) ? zg + s - N2 : zg + s;
-                                const C v = W[pk0 + plane * zw];
+                                C v;
+                                if (ACCU && z + s < ZL && TDKS_ZOK(z + s)) {
+                                    v = acc[ACCU ? (z + s < ZL ? z + s : 0) : 0];
+                                } else {
+                                    const int zw = (zg + s >= N2) ? zg + s - N2 : zg + s;
+                                    v = W[pk0 + plane * zw];
+                                }
                                 if (s == 1) u1 = v; else u2 = v;
                             }
                         }
