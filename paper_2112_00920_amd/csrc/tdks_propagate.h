@@ -882,6 +882,20 @@ void k_propagate(PropArgs a) {
                         zw = zw < 0 ? zw + N2 : (zw >= N2 ? zw - N2 : zw);
                         zn[s] = W[pb + plane * zw];
                     }
+                    // FP32 records in device memory: this point's range and first record are
+                    // requested before the stencil arithmetic, which covers their latency
+                    int se0 = 0, se1 = 0;
+                    PtRec<R> rfirst;
+                    rfirst.pk = 0u;
+                    rfirst.g = R(0);
+                    if (SL != 1 && sizeof(R) == 4) {
+                        se0 = ptpl ? int(ptp_l[p]) : pt_ptr[p];
+                        se1 = ptpl ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
+                        if (se0 < se1) {
+                            rfirst.pk = pt_recs[se0].pk;
+                            rfirst.g = pt_recs[se0].g;
+                        }
+                    }
                     C cen;
                     cen.x = R(0);
                     cen.y = R(0);
@@ -992,15 +1006,16 @@ void k_propagate(PropArgs a) {
                             scatter_one(rec.pk, rec.g, q);
                         }
                     } else if (sizeof(R) == 4) {  // FP32: the same records in global memory, one load each
-                        const auto *recs = pt_recs;
-                        const int e0 = ptpl ? int(ptp_l[p]) : pt_ptr[p];
-                        const int e1 = ptpl ? int(ptp_l[p + 1]) : pt_ptr[p + 1];
-                        for (int e = e0; e < e1; ++e) {
-                            PtRec<R> rec;
-                            rec.pk = recs[e].pk;
-                            rec.g = recs[e].g;
+                        PtRec<R> rec = rfirst;
+                        for (int e = se0; e < se1; ++e) {
+                            PtRec<R> nx = rec;  // the next record is requested before this one is used
+                            if (e + 1 < se1) {
+                                nx.pk = pt_recs[e + 1].pk;
+                                nx.g = pt_recs[e + 1].g;
+                            }
                             const Q4 q = *reinterpret_cast<const Q4 *>(reinterpret_cast<const char *>(AB) + (rec.pk & 0xffffu));
                             scatter_one(rec.pk, rec.g, q);
+                            rec = nx;
                         }
                     } else {  // FP64: packed entries and radial factors from their own arrays
                         const int e1 = pt_ptr[p + 1];
