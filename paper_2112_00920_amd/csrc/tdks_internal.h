@@ -93,8 +93,9 @@ struct WorkItem {
 };
 
 // Built (column-segment length ZL, max threads per workgroup, min waves per SIMD) triples
-// of the propagation kernel.  N3 must be a multiple of ZL; the block is N1 N2 (N3 / ZL)
-// threads rounded up to 64.
+// of the propagation kernel.  N3 must be a multiple of ZL (or a ragged tiling is used); the
+// block is N1 N2 (N3 / ZL) threads rounded up to whole waves, and a block of more than 8
+// waves is padded to 16.
 #define TDKS_PROPAGATE_CONFIGS(X) \
     X(2, 512, 2) X(3, 512, 2) X(4, 512, 2) X(6, 512, 2) X(8, 512, 2) X(12, 512, 2) X(16, 512, 2) \
     X(4, 512, 4) X(6, 512, 4) X(8, 512, 4) X(4, 1024, 4) X(8, 1024, 4) X(10, 1024, 4)

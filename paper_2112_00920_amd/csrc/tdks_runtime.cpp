@@ -517,8 +517,8 @@ int build_potential_and_tables(InstHost &I, const tdks_instance_desc &d, TableSe
 // block's waves in turn (task t by wave t mod NW). The split minimises the busiest wave's work,
 // counted as 64-chunk passes plus 0.4 of a pass for each task's reduction, over two families:
 // every atom cut into m equal ranges, and ranges of 64 j chunks; ties go to fewer tasks (LDS).
-// E.g. 8 atoms on 13 waves (20^3, 832 threads): two tasks per atom left three waves with two
-// tasks each, twice the others' work.
+// E.g. 8 atoms on 13 waves (a 20^3 block of 832 threads, before blocks were padded to 16
+// waves): two tasks per atom left three waves with two tasks each, twice the others' work.
 // len_mode 0: every atom cut into arg equal ranges; 1: ranges of 64 arg chunks
 std::vector<int2> split_tasks(const std::vector<int> &atom_chunk, int nat, int len_mode, int arg) {
     std::vector<int2> task;
@@ -614,6 +614,15 @@ bool choose_tiling(const int N[3], int fp64, int want_block, int want_w, int &zl
         const int nseg = (N[2] + z - 1) / z;
         int b = N[0] * N[1] * nseg;
         b = (b + 63) / 64 * 64;
+        // a block of more than 8 waves runs alone on its CU (4 waves per SIMD, and its LDS):
+        // padded to the 16 waves the CU then holds, its wave-parallel phases (projection tasks,
+        // scatter coefficients, the current's chunk tasks) spread over all of them (20^3: 13 ->
+        // 16 waves, HHG step 17.16 -> 15.89 ms); a requested block size at least the one the
+        // segments need is taken as given
+        if (want_block >= b && want_block <= 1024 && want_block % 64 == 0)
+            b = want_block;
+        else if (want_block <= 0 && b > 512 && b < 1024)
+            b = 1024;
         // more than 512 threads need 4 waves per SIMD; otherwise short FP32 segments fit the
         // 128-register budget of 4 waves, longer ones (and FP64) run at 2
         int w = (b > 512) ? 4 : (want_w > 0 ? want_w : ((!fp64 && z <= 4) ? 4 : 2));
