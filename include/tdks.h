@@ -146,7 +146,10 @@ typedef struct tdks_options {
     int k_per_group;      /* k-points per workgroup (0 = 4 for instances with at
                              least 256 k-points when the context has at least
                              16384 (k, band group) items, else 1)                 */
-    int block_size;       /* threads per workgroup (0 = automatic)                 */
+    int block_size;       /* threads per workgroup (0 = automatic: the z-segments'
+                             threads rounded up to whole waves, a block of more
+                             than 8 waves padded to 16; a request at least the
+                             segments' count, up to 1024, is taken as given)      */
     int graph_steps;      /* steps captured per HIP graph (0 = 16; <0 disables)    */
     int waves_per_simd;   /* occupancy target of the propagation kernel: 2 or 4
                              (0 = automatic); selects the register budget          */
