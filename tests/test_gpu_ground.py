@@ -161,6 +161,31 @@ def test_ragged_grid_and_many_bands(tdks, precision):
         assert abs(res[i] - r[-1]) < (1e-9 if precision == "fp64" else 1e-3) * r[-1]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_padded_block_grid(tdks, precision):
+    """A 20^3 grid: 800 column segments of 10 points in a block padded to 1024 threads,
+    whose extra waves own no segment but take projection, coefficient and current tasks; the
+    imaginary-time kernel and the orthonormalisation against the oracle's route, 2 iterations."""
+    sp = _species()
+    inst = W.make_instance("diamond8", (20, 20, 20), 4, [sp], W.KSpec((2, 1, 1)))
+    u0 = W.random_orbitals(91, inst.n_k, inst.n_bands, inst.grid, inst.omega)
+    tau = 0.05  # the 20^3 kinetic bound (about 30 Ha) allows tau below 0.09
+    with tdks.Propagator([inst], precision=precision) as p:
+        til = p.tiling()
+        p.load_orbitals(0, u0)
+        res = p.ground_state(2, tau, 0.5)
+        got = p.get_orbitals(0)
+    _say(f"  {precision}: tiling {til}")
+    assert til["block"] == 1024 and til["zl"] == 10
+    if precision == "fp32":
+        u0 = u0.astype(np.complex64).astype(np.complex128)
+    u, rho, v, r = G.imaginary_time_scf(System(inst), u0, tau, 0.5, 2)
+    eu = np.max(np.abs(got - u))
+    _say(f"  {precision}: u err {eu:.2e}, residual {res[0]:.3e}")
+    assert eu < (1e-10 if precision == "fp64" else 2e-5)
+    assert abs(res[0] - r[-1]) < (1e-9 if precision == "fp64" else 1e-3) * r[-1]
+
+
 @pytest.mark.parametrize("bands", [(1, 16), (17, 32)])
 def test_band_counts_at_block_edges(tdks, bands):
     """Band counts at the edges of the orthonormalisation's 16-band blocks: one band and
